@@ -1,0 +1,320 @@
+#!/usr/bin/env python3
+"""Throughput of the ERPP particle/fluid coupling step on one MI355X.
+
+Default workload: the shear-flow-shaped box (256 x 128 x 128 nodes,
+4pi x 2pi x 2pi, 4e5 particles, 70% in 2000 Gaussian blobs, mean shear S = 1
+plus a k^-5/3 fluctuation, three Stokes-time populations, sigma = 1.5 dx, M = 8,
+dt = 2e-4), run in the FP32 tiled path (FP64 particle integration) as a
+captured HIP graph per step.  Inputs are seeded synthetic arrays already
+resident in HBM when the timed region starts.
+
+Prints ONE JSON line: particle-steps/s over the timed steps, the roofline of the
+dominant kernel (HIP-event durations of each stage, measured in this run), the
+plain FP64 GPU path on the same inputs, the accuracy against the FP64 oracle on a
+particle sample and a node window, and the oracle itself timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s and %HBM peak, FP32 batched vs FP64 plain, at ≤1e-5 rel L2"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+LDS_PEAK_TOPS = 256 * 32 * 2.4e9 / 1e12     # 256 CUs x 32 banks x 2.4 GHz (dword ops)
+STAGES_FAST = ["bin_count", "scan", "eval", "scatter", "update"]
+KERNELS_FAST = ["k_bin_count", "k_scan", "k_eval", "k_scatter", "k_update"]
+WORKLOADS = {"c1": 1, "c2": 2, "c3": 3, "c3cube": 33, "c4": 4, "c5": 5}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=16)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--tile", default=None, help="tile as X,Y,Z (skips the autotuner)")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stage-steps", type=int, default=10)
+    return ap.parse_args()
+
+
+def byte_model(boxes, M):
+    """Algorithmic bytes per step and per kernel launch (FP32 path)."""
+    np_tot = sum(b.np_ for b in boxes)
+    ng_tot = sum(int(np.prod(b.n)) for b in boxes)
+    touched = sum(min(int(np.prod(b.n)), 8 * b.np_) for b in boxes)
+    nbins = None
+    step = 224 * np_tot + 12 * ng_tot + 12 * touched
+    per_kernel = {
+        # delayed position read, rank write, histogram atomic
+        "bin_count": 32 * np_tot,
+        # delayed position + drag, rank, bin start read; 32-byte record written
+        "eval": (24 + 12 + 4 + 4 + 32) * np_tot,
+        # records read once, forcing written once (12 B per node)
+        "scatter": 32 * np_tot + 12 * ng_tot,
+        # x, v, tau, level n-1-M (x, D) read; x, v, ring slot written; carrier
+        "update": (24 + 24 + 4 + 36 + 24 + 24 + 36) * np_tot + 12 * touched,
+    }
+    return step, per_kernel, nbins
+
+
+def scatter_flops(boxes, stencil_nodes):
+    # 7 flops per stencil node: w = gx * gyz (1), three multiply-adds (6)
+    return sum(7.0 * stencil_nodes(b) * b.np_ for b in boxes)
+
+
+def stencil_nodes_of(box):
+    s = box.spec.sigma_dx * box.spec.cutoff
+    # mean lattice count of the ball of radius s (in grid units)
+    return 4.0 / 3.0 * math.pi * s ** 3
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("fast.hip", "erpp_device.hpp", "erpp_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1405_6969_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, launches_units):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, when they
+    were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except Exception:
+        return None
+    if data.get("kernel_sha") != kernel_source_hash():
+        return None
+    ent = data.get("kernels", {}).get(kernel)
+    if not ent:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU "
+              f"sharding is described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    import paper_1405_6969_amd as erpp
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    w = workloads.config(WORKLOADS[args.workload])
+    boxes = workloads.make_boxes(w)
+    log(f"[bench] workload {w.name}: {len(boxes)} box(es), "
+        f"{sum(b.np_ for b in boxes)} particles, inputs in {time.time() - t0:.1f}s")
+    M, dt = w.M, w.dt
+    W, K = max(args.warmup, M + 1), args.steps
+
+    def upload(prec):
+        out = []
+        for b in boxes:
+            u = b.u.astype(np.float32) if prec == erpp.F32_FAST else b.u
+            s = b.spec
+            out.append(erpp.device_box(b.n, b.L, b.x, b.v, b.tau, u, M, b.m_p, s.rho_f, s.nu,
+                                       b.sigma, s.cutoff, s.shear, precision=prec))
+        return out
+
+    # ------------------------------------------------------- FP32 tiled path
+    dbs = upload(erpp.F32_FAST)
+    plan = erpp.Plan(dbs, M, dt, precision=erpp.F32_FAST)
+    steps_done = 0
+    plan.run(0, W, graph=False)
+    steps_done += W
+    torch.cuda.synchronize()
+    if args.tile:
+        plan.set_tile(tuple(int(a) for a in args.tile.split(",")))
+    elif not args.no_tune:
+        plan.tune(None)
+    tile = plan.get_tile()
+    plan.run(steps_done, 4, graph=True)       # capture + warm replays
+    steps_done += 4
+    torch.cuda.synchronize()
+    log(f"[bench] warm-up {steps_done} steps done, tile {tile}")
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    plan.run(steps_done, K, graph=True)
+    e1.record()
+    torch.cuda.synchronize()
+    steps_done += K
+    ms_step = e0.elapsed_time(e1) / K
+    np_tot = sum(b.np_ for b in boxes)
+    value = np_tot / (ms_step * 1e-3)
+    log(f"[bench] timed {K} steps: {ms_step * 1e3:.1f} us/step, {value:.3e} particle-steps/s")
+
+    stage_ms = plan.stage_times(steps_done, args.stage_steps)
+    steps_done += args.stage_steps
+    torch.cuda.synchronize()
+    log("[bench] stage ms: " + ", ".join(f"{n}={t * 1e3:.1f}us" for n, t in zip(STAGES_FAST, stage_ms)))
+
+    step_bytes, kbytes, _ = byte_model(boxes, M)
+    dom = int(np.argmax(stage_ms))
+    dom_name = STAGES_FAST[dom]
+    dom_bytes = kbytes.get(dom_name, 0)
+    achieved = dom_bytes / (stage_ms[dom] * 1e-3) / 1e9
+    roof = {"kernel": KERNELS_FAST[dom], "bound": "hbm", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_from_profiles(KERNELS_FAST[dom], None),
+            "algorithmic_bytes_per_launch": dom_bytes,
+            "avg_launch_us": round(stage_ms[dom] * 1e3, 2)}
+    if dom_name == "scatter":
+        fl = scatter_flops(boxes, stencil_nodes_of)
+        lds_ops = 3.0 * sum(stencil_nodes_of(b) * b.np_ for b in boxes)
+        roof["secondary"] = {
+            "fp32_tflops": round(fl / (stage_ms[dom] * 1e-3) / 1e12, 2),
+            "fp32_peak_tflops": FP32_PEAK_TFLOPS,
+            "lds_atomic_tops": round(lds_ops / (stage_ms[dom] * 1e-3) / 1e12, 3),
+            "lds_peak_tops": round(LDS_PEAK_TOPS, 2)}
+    step_gbs = step_bytes / (ms_step * 1e-3) / 1e9
+
+    # ------------------------------------------------------- FP64 plain path
+    plain = None
+    if not args.no_plain:
+        pdb = upload(erpp.F64_PLAIN)
+        pplan = erpp.Plan(pdb, M, dt, precision=erpp.F64_PLAIN)
+        pplan.run(0, M + 1, graph=False)
+        torch.cuda.synchronize()
+        nrep = 5
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        pplan.run(M + 1, nrep, graph=True)
+        b.record()
+        torch.cuda.synchronize()
+        pms = a.elapsed_time(b) / nrep
+        pplan.close()
+        del pdb
+        torch.cuda.empty_cache()
+        plain = {"ms_per_step": round(pms, 4), "value": np_tot / (pms * 1e-3),
+                 "speedup_fp32_vs_fp64_plain": round(pms / ms_step, 2)}
+        log(f"[bench] FP64 plain: {pms * 1e3:.1f} us/step (x{pms / ms_step:.1f})")
+
+    # ------------------------------------------------------- accuracy vs oracle
+    accuracy = None
+    if not args.no_check and len(boxes) == 1:
+        accuracy = check_accuracy(boxes[0], dbs[0], w, steps_done)
+        log(f"[bench] accuracy {accuracy}")
+
+    # ------------------------------------------------------- oracle on the host
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(boxes[0], w)
+        log(f"[bench] oracle {cpu}")
+
+    plan.close()
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": round(ms_step, 6), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded; no dataset)",
+        "config": {"workload": w.name, "boxes": len(boxes),
+                   "grid": list(boxes[0].n) if len(boxes) == 1 else "ensemble",
+                   "particles": np_tot, "M": M, "dt": dt, "sigma_dx": boxes[0].spec.sigma_dx,
+                   "tile": list(tile), "graph": True, "integration": "f64"},
+        "hbm_frac_step": round(step_gbs / HBM_PEAK_GBS, 4),
+        "algorithmic_bytes_per_step": step_bytes,
+        "stage_us": {n: round(t * 1e3, 2) for n, t in zip(STAGES_FAST, stage_ms)},
+        "roofline": roof,
+        "fp64_plain": plain,
+        "accuracy": accuracy,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def check_accuracy(box, db, w, steps_done):
+    """Oracle on (a) 4000 random particles for v and (b) the particles that can
+    reach a 32^3 node window for f; particles are independent under a frozen
+    carrier, so both subsets are exact."""
+    import torch
+    import oracle
+
+    M, dt = w.M, w.dt
+    rng = np.random.default_rng(20250101)
+    P = oracle.params_for_box(box, M, dt, 1)
+    u = box.u.astype(np.float32).astype(np.float64)
+    sample = rng.choice(box.np_, size=min(4000, box.np_), replace=False)
+    run = oracle.Run(P, u, box.x[:, sample], box.v[:, sample], box.tau[sample])
+    for _ in range(steps_done):
+        run.step(want_f=False)
+    v_gpu = db.v.cpu().numpy()[:, sample]
+    ev = float(np.linalg.norm(v_gpu - run.v) / np.linalg.norm(run.v))
+    # window: 32^3 nodes at a seeded offset; particles within 3 sigma + drift
+    wn = tuple(min(32, n) for n in box.n)
+    lo = tuple(int(rng.integers(0, n)) for n in box.n)
+    vmax = float(np.max(np.abs(box.v))) + float(np.max(np.abs(box.u))) \
+        + abs(box.spec.shear) * box.L[1]
+    margin = box.spec.cutoff * box.sigma + 2.0 * vmax * steps_done * dt + 2 * box.dx[0]
+    keep = np.ones(box.np_, bool)
+    for d in range(3):
+        c = (lo[d] + 0.5 * (wn[d] - 1)) * box.dx[d]
+        dd = box.x[d] - c
+        dd -= box.L[d] * np.round(dd / box.L[d])
+        half = 0.5 * (wn[d] - 1) * box.dx[d] + margin
+        keep &= np.abs(dd) <= half
+    idx = np.nonzero(keep)[0]
+    run2 = oracle.Run(P, u, box.x[:, idx], box.v[:, idx], box.tau[idx])
+    for n in range(steps_done - 1):
+        run2.step(want_f=False)
+    fo, _ = run2.step(want_f=True, lo=lo, wn=wn)
+    fg = db.f.double().cpu().numpy()
+    iz = (np.arange(wn[2]) + lo[2]) % box.n[2]
+    iy = (np.arange(wn[1]) + lo[1]) % box.n[1]
+    ix = (np.arange(wn[0]) + lo[0]) % box.n[0]
+    fw = fg[:, iz][:, :, iy][:, :, :, ix]
+    nrm = np.linalg.norm(fo)
+    ef = float(np.linalg.norm(fw - fo) / nrm) if nrm > 0 else None
+    return {"rel_l2_v_sample": ev, "v_sample": int(sample.size), "rel_l2_f_window": ef,
+            "f_window": {"lo": list(lo), "n": list(wn), "particles": int(idx.size)},
+            "steps": steps_done}
+
+
+def cpu_baseline(box, w):
+    """The oracle as it stands, one full step with the delayed forcing live."""
+    import oracle
+    M, dt = w.M, w.dt
+    P = oracle.params_for_box(box, M, dt, 1)
+    u = box.u.astype(np.float32).astype(np.float64)
+    run = oracle.Run(P, u, box.x, box.v, box.tau)
+    for _ in range(M):
+        run.step(want_f=False)
+    t = time.perf_counter()
+    run.step(want_f=True)
+    dtm = time.perf_counter() - t
+    return {"value": round(box.np_ / dtm, 1), "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle", "seconds": round(dtm, 2),
+            "sample": f"one full step (step {M}, forcing live) of {w.name}: "
+                      f"{box.np_} particles, {int(np.prod(box.n))} nodes, single thread"}
+
+
+if __name__ == "__main__":
+    main()

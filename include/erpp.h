@@ -1,0 +1,172 @@
+/*
+ * erpp.h -- C ABI of the MI355X (gfx950) ERPP particle/fluid momentum-coupling
+ * step.
+ *
+ * Method: Gualtieri, Picano, Sardina & Casciola, "Exact regularized point
+ * particle method for multi-phase flows in the two-way coupling regime",
+ * arXiv:1405.6969.  One coupling step n of every box does, in order:
+ *
+ *   1. bin      -- sort the particles whose drag is being injected by grid tile
+ *                  (locality structure for the scatter; not in the paper);
+ *   2. evaluate -- for each particle read the history ring at level n-M
+ *                  (position and drag delayed by eps_R = M dt, Sec. 2.3,
+ *                  eq. velo_reg_eq) and form the normalised Gaussian amplitude;
+ *                  read level n-1-M for the closed-form self-disturbance of
+ *                  App. E (eq. disturbance_velo);
+ *   3. scatter  -- forcing on the grid, -(1/rho_f) sum_p D_p(t-eps_R)
+ *                  g[x - x_p(t-eps_R), eps_R] (Sec. 2.4,
+ *                  eq. ns_regularized_filtered), g cut at |x - x_p| <= 3 sigma_R
+ *                  (Sec. 3.2) and normalised per particle on the lattice;
+ *   4. gather   -- carrier velocity at each particle by trilinear interpolation
+ *                  (plus an optional analytic mean shear S (y - Ly/2) e_x);
+ *   5. update   -- Stokes drag D = m_p (u~ - v)/tau_p with u~ the carrier minus
+ *                  the self-disturbance (Sec. 2.5, eqs. force_stokes_drag and
+ *                  particle_motion), stored in ring slot n mod (M+1) with x^n,
+ *                  then explicit Euler x^{n+1} = x^n + dt v^n,
+ *                  v^{n+1} = v^n + dt D/m_p, periodic wrap.
+ *
+ * Readings of the paper used throughout: sigma_R is given directly; the delay
+ * is eps_R = M dt; the self-disturbance width is sigma_s^2 = sigma_R^2 + 2 nu dt
+ * (App. E: sigma^2 = 2 nu (eps_R + dt)); its -dt/rho_f prefactor (App. E,
+ * eqs. forcing_step and pseudo_velo_num) is kept; levels before t = 0 carry no
+ * drag (f = 0 for n < M, no self term for n <= M).
+ *
+ * Conventions
+ *   - Every pointer in erpp_box is DEVICE memory owned by the caller; the
+ *     library never frees or reallocates it.  The plan owns only its scratch.
+ *   - Layouts: grid fields [3][Nz][Ny][Nx] (x fastest), nodes at x_i = i L/N;
+ *     particle arrays [3][np] (structure of arrays); rings [M+1][3][np].
+ *   - Precision ERPP_F64_PLAIN: u, f, ring_d are double; every stage in FP64.
+ *     Precision ERPP_F32_FAST: u, f, ring_d are float; kernel evaluation and
+ *     grid accumulation in FP32, cell indices, positions, velocities and the
+ *     drag in FP64.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     asynchronous on it; errors from earlier asynchronous work surface at a
+ *     later call or at erpp_plan_destroy.
+ *   - No C++ exception crosses this ABI.  Every call validates its arguments
+ *     before it launches anything; on error nothing is launched and
+ *     erpp_last_error() describes the problem (thread-local string).
+ */
+#ifndef ERPP_H
+#define ERPP_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ERPP_OK = 0,
+    ERPP_EINVAL = -1,       /* NULL pointer, np < 0, M < 1, dt <= 0, bad index ... */
+    ERPP_ENOMEM = -2,       /* device allocation of plan scratch failed           */
+    ERPP_EHIP = -3,         /* a HIP runtime call failed                          */
+    ERPP_EGEOM = -4,        /* grid too small for the stencil (N < 2 R_c + 2),
+                               L <= 0, sigma <= 0 or cutoff <= 0                  */
+    ERPP_EUNSUPPORTED = -5  /* outside the library's limits (a dimension > 2048 in
+                               x/y or > 1024 in z, more than 2^31-1 particles or
+                               nodes per box)                                     */
+} erpp_status;
+
+typedef enum {
+    ERPP_F64_PLAIN = 0,     /* plain FP64 path (global FP64 atomics, no binning)  */
+    ERPP_F32_FAST = 1       /* binned, LDS-tiled FP32 scatter, FP64 integration   */
+} erpp_precision;
+
+/* One periodic box.  All pointers: device memory, caller-owned. */
+typedef struct {
+    int32_t n[3];           /* grid nodes Nx, Ny, Nz                               */
+    double  L[3];           /* box lengths                                         */
+    int64_t np;             /* particles (0 allowed)                               */
+    double *x;              /* [3][np] positions in/out: x^n -> x^{n+1}, in [0,L)  */
+    double *v;              /* [3][np] velocities in/out: v^n -> v^{n+1}           */
+    double *ring_x;         /* [M+1][3][np] history of positions                   */
+    void   *ring_d;         /* [M+1][3][np] history of drags (float or double)     */
+    const float *tau;       /* [np] Stokes times tau_p                             */
+    const void  *u;         /* [3][Nz][Ny][Nx] carrier velocity (float or double)  */
+    void   *f;              /* [3][Nz][Ny][Nx] forcing output, acceleration
+                               (float or double); fully overwritten by a scatter   */
+    double  m_p;            /* particle mass                                       */
+    double  rho_f;          /* fluid density                                       */
+    double  nu;             /* kinematic viscosity (self-disturbance width)        */
+    double  sigma;          /* regularisation width sigma_R                        */
+    double  cutoff;         /* stencil radius in units of sigma_R (3)              */
+    double  shear;          /* mean shear S, U_x = S (y - Ly/2); 0 = none.  A
+                               particle crossing y = 0 / Ly gets v_x -/+= S Ly     */
+} erpp_box;
+
+typedef struct erpp_plan erpp_plan;   /* opaque: copies of the boxes, scratch,
+                                         tile shape, captured graph            */
+
+/* Create a plan for `nbox` boxes (copied; the pointers inside must stay valid
+ * for the plan's lifetime).  M >= 1 is the delay in steps (eps_R = M dt),
+ * self_correction 1 removes the self-disturbance (App. E), 0 keeps it.
+ * Allocates the plan's scratch on the current device.  Returns ERPP_EINVAL,
+ * ERPP_EGEOM, ERPP_EUNSUPPORTED or ERPP_ENOMEM without creating anything. */
+erpp_status erpp_plan_create(erpp_plan **plan, const erpp_box *boxes, int32_t nbox,
+                             int32_t M, double dt, erpp_precision precision,
+                             int32_t self_correction, void *stream);
+
+/* Scatter tile shape (nodes per tile in x, y, z) of an ERPP_F32_FAST plan.
+ * Each entry in [4, 64], tile_x * tile_y * tile_z <= 8192 and the LDS copy of
+ * the tile (24 bytes per node, rows padded by one node) <= 150 KiB.  Per box the
+ * tile is clipped so that a stencil never wraps onto a tile twice.  Invalidates
+ * a captured graph. */
+erpp_status erpp_plan_set_tile(erpp_plan *plan, const int32_t tile[3]);
+erpp_status erpp_plan_get_tile(const erpp_plan *plan, int32_t tile[3]);
+
+/* Autotuner (ERPP_F32_FAST): times every candidate tile shape on the plan's own
+ * boxes (scatter of the current ring contents, which are only read) and keeps
+ * the fastest.  With cache_path != NULL the choice is read from / appended to
+ * that text file, keyed by the geometry; a hit skips the timing.  Synchronises
+ * `stream`.  On ERPP_F64_PLAIN plans it is a no-op. */
+erpp_status erpp_plan_tune(erpp_plan *plan, const char *cache_path, void *stream);
+
+/* Number of scatter bins (tiles) of box `ibox` for erpp_bin. */
+erpp_status erpp_plan_bins(const erpp_plan *plan, int32_t ibox, int32_t *nbin);
+
+/* Bin `pos` ([3][np] device FP64 positions of box ibox, e.g. x^n or a ring
+ * level) by the plan's tiles: key[p] = (k Ny + j) Nx + i is the cell of the
+ * wrapped position (i = min(floor(x/dx), N-1)); perm lists the particles grouped
+ * by tile in ascending tile order, bin_start[nbin+1] delimits the groups (order
+ * inside a group unspecified).  key, perm, bin_start: device, caller-owned,
+ * sizes np, np, nbin+1. */
+erpp_status erpp_bin(erpp_plan *plan, int32_t ibox, const double *pos, int32_t *key,
+                     int32_t *perm, int32_t *bin_start, void *stream);
+
+/* Stages 1-3 for every box: write f for step `step` from ring level step-M
+ * (f = 0 when step < M).  The ring is only read. */
+erpp_status erpp_scatter(erpp_plan *plan, int64_t step, void *stream);
+
+/* Stage 4 for every box: u_p = trilinear(u, x) + S (y - Ly/2) e_x, FP64,
+ * [3][np] per box, boxes concatenated in plan order (device, caller-owned). */
+erpp_status erpp_gather(erpp_plan *plan, double *u_p, void *stream);
+
+/* Stages 1-5 for every box (one coupling step n = step). */
+erpp_status erpp_step(erpp_plan *plan, int64_t step, void *stream);
+
+/* Steps step0 .. step0+nsteps-1.  use_graph = 1 captures the step once in a
+ * HIP graph (step index kept in device memory) and replays it. */
+erpp_status erpp_run(erpp_plan *plan, int64_t step0, int64_t nsteps, int32_t use_graph,
+                     void *stream);
+
+/* Measurement: run steps step0 .. step0+nsteps-1 (nsteps >= 1) stage by stage
+ * without a graph, with a HIP event recorded on `stream` after every stage, and
+ * return in ms[k] the average duration (milliseconds) of stage k:
+ *   ERPP_F32_FAST:  0 tile histogram, 1 scan, 2 evaluate, 3 tiled scatter,
+ *                   4 gather + self term + update;
+ *   ERPP_F64_PLAIN: 0 zero the forcing, 1 (nothing), 2 evaluate,
+ *                   3 atomic scatter, 4 gather + self term + update.
+ * The steps are real steps (particles advance).  Synchronises `stream`. */
+erpp_status erpp_stage_times(erpp_plan *plan, int64_t step0, int64_t nsteps, double ms[5],
+                             void *stream);
+
+/* Release the plan's scratch and graph.  NULL-safe.  Synchronises the device. */
+void erpp_plan_destroy(erpp_plan *plan);
+
+const char *erpp_status_string(erpp_status status);
+const char *erpp_last_error(void);   /* thread-local detail of the last failure */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ERPP_H */

@@ -1,0 +1,545 @@
+// api.hip -- C ABI of the ERPP coupling step (see include/erpp.h): argument
+// validation, plan construction, stage dispatch, HIP-graph replay and the tile
+// autotuner.  No C++ exception leaves this file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "erpp_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+erpp_status fail(erpp_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+erpp_status hip_fail(hipError_t e, const char *what) {
+    return fail(ERPP_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_OR_RETURN(expr)                              \
+    do {                                                 \
+        hipError_t _e = (expr);                          \
+        if (_e != hipSuccess) return hip_fail(_e, #expr); \
+    } while (0)
+
+__global__ void k_set_step(int64_t *s, int64_t n) { *s = n; }
+__global__ void k_advance_step(int64_t *s) { *s += 1; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Stencil offsets that can reach the cut-off sphere: m in [-floor(Rn), floor(Rn)+1]
+// with Rn = cutoff sigma / dx (a small margin keeps the range a superset when
+// Rn rounds just below an integer).
+void stencil_range(double rc, double dx, int32_t &mlo, int32_t &mhi) {
+    double Rn = rc / dx;
+    int32_t f = (int32_t)std::floor(Rn + 1e-6);
+    mlo = -f;
+    mhi = f + 1;
+}
+
+void free_scratch(erpp_plan *p) {
+    erpp::Scratch &s = p->s;
+    (void)hipFree(s.count);
+    (void)hipFree(s.start);
+    (void)hipFree(s.rank);
+    (void)hipFree(s.rec);
+    (void)hipFree(s.binmax);
+    (void)hipFree(s.pamp);
+    (void)hipFree(s.pphi);
+    (void)hipFree(s.pbase);
+    (void)hipFree(s.step);
+    s = erpp::Scratch();
+    (void)hipFree(p->dbox);
+    p->dbox = nullptr;
+}
+
+void drop_graph(erpp_plan *p) {
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
+}
+
+template <typename T>
+hipError_t alloc(T **ptr, size_t count) {
+    if (count == 0) count = 1;
+    return hipMalloc((void **)ptr, sizeof(T) * count);
+}
+
+erpp_status upload_boxes(erpp_plan *p) {
+    if (p->prec == ERPP_F32_FAST) HIP_OR_RETURN(erpp::fast_prepare_lds(p->lds_bytes));
+    HIP_OR_RETURN(hipMemcpy(p->dbox, p->hbox.data(), sizeof(erpp::DevBox) * p->hbox.size(),
+                            hipMemcpyHostToDevice));
+    return ERPP_OK;
+}
+
+// (Re)allocate the bin arrays after a tile change.
+erpp_status alloc_bins(erpp_plan *p) {
+    (void)hipFree(p->s.count);
+    (void)hipFree(p->s.start);
+    (void)hipFree(p->s.binmax);
+    p->s.count = nullptr;
+    p->s.start = nullptr;
+    p->s.binmax = nullptr;
+    if (alloc(&p->s.count, (size_t)p->nbins_total) != hipSuccess ||
+        alloc(&p->s.start, (size_t)p->nbins_total + 1) != hipSuccess ||
+        alloc(&p->s.binmax, (size_t)p->nbins_total) != hipSuccess)
+        return fail(ERPP_ENOMEM, "bin arrays (%lld bins)", (long long)p->nbins_total);
+    HIP_OR_RETURN(hipMemset(p->s.binmax, 0, sizeof(uint32_t) * (size_t)std::max<int64_t>(p->nbins_total, 1)));
+    HIP_OR_RETURN(hipMemset(p->s.count, 0, sizeof(int32_t) * (size_t)std::max<int64_t>(p->nbins_total, 1)));
+    HIP_OR_RETURN(hipMemset(p->s.start, 0, sizeof(int32_t) * (size_t)(p->nbins_total + 1)));
+    return ERPP_OK;
+}
+
+erpp_status check_tile(const int32_t tile[3]) {
+    if (!tile) return fail(ERPP_EINVAL, "tile is NULL");
+    for (int d = 0; d < 3; ++d)
+        if (tile[d] < 4 || tile[d] > erpp::kMaxTileDim)
+            return fail(ERPP_EINVAL, "tile[%d]=%d outside [4, %d]", d, tile[d], erpp::kMaxTileDim);
+    if ((int64_t)tile[0] * tile[1] * tile[2] > erpp::kMaxTileVol)
+        return fail(ERPP_EINVAL, "tile volume %lld > %d",
+                    (long long)tile[0] * tile[1] * tile[2], erpp::kMaxTileVol);
+    if (erpp::scatter_lds_bytes(tile) > erpp::kMaxScatterLds)
+        return fail(ERPP_EINVAL, "tile needs %zu bytes of LDS (> %zu)", erpp::scatter_lds_bytes(tile),
+                    erpp::kMaxScatterLds);
+    return ERPP_OK;
+}
+
+hipStream_t as_stream(void *s) { return (hipStream_t)s; }
+
+erpp_status run_stages(erpp_plan *p, hipStream_t st, bool update) {
+    hipError_t e;
+    if (p->prec == ERPP_F32_FAST) {
+        e = erpp::fast_scatter_stages(p, st);
+        if (e == hipSuccess && update) e = erpp::fast_update_stage(p, st);
+    } else {
+        e = erpp::plain_scatter_stages(p, st);
+        if (e == hipSuccess && update) e = erpp::plain_update_stage(p, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return ERPP_OK;
+}
+
+}  // namespace
+
+namespace erpp {
+
+hipError_t set_step(erpp_plan *p, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, st, p->s.step, n);
+    return hipGetLastError();
+}
+
+hipError_t advance_step(erpp_plan *p, hipStream_t st) {
+    hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(1), 0, st, p->s.step);
+    return hipGetLastError();
+}
+
+void fill_box_tiles(erpp_plan *p) {
+    int64_t bin = 0, bp = 0, bt = 0, br = 0;
+    for (auto &B : p->hbox) {
+        for (int d = 0; d < 3; ++d) {
+            int32_t ext = B.mhi[d] - B.mlo[d] + 1;
+            int32_t T = std::min(p->tile[d], B.n[d] - ext);
+            if (T < 1) T = 1;
+            B.T[d] = T;
+            B.ntile[d] = (B.n[d] + T - 1) / T;
+        }
+        B.bin_off = bin;
+        bin += (int64_t)B.ntile[0] * B.ntile[1] * B.ntile[2];
+        B.blk_p = bp;
+        bp += (B.np + kBlock - 1) / kBlock;
+        B.blk_t = bt;
+        bt += (int64_t)B.ntile[0] * B.ntile[1] * B.ntile[2];
+        B.rows = (int64_t)(B.mhi[1] - B.mlo[1] + 1) * (B.mhi[2] - B.mlo[2] + 1);
+        B.blk_r = br;
+        br += (B.np * B.rows + kBlock - 1) / kBlock;
+    }
+    p->nbins_total = bin;
+    p->pblocks = bp;
+    p->tblocks = bt;
+    p->pblocks_rows = br;
+    p->lds_bytes = scatter_lds_bytes(p->tile);
+}
+
+}  // namespace erpp
+
+extern "C" {
+
+const char *erpp_status_string(erpp_status s) {
+    switch (s) {
+        case ERPP_OK: return "ERPP_OK";
+        case ERPP_EINVAL: return "ERPP_EINVAL: invalid argument";
+        case ERPP_ENOMEM: return "ERPP_ENOMEM: device allocation failed";
+        case ERPP_EHIP: return "ERPP_EHIP: HIP runtime error";
+        case ERPP_EGEOM: return "ERPP_EGEOM: grid too small for the stencil or bad geometry";
+        case ERPP_EUNSUPPORTED: return "ERPP_EUNSUPPORTED: outside the library's limits";
+    }
+    return "unknown erpp_status";
+}
+
+const char *erpp_last_error(void) { return g_err.c_str(); }
+
+erpp_status erpp_plan_create(erpp_plan **out, const erpp_box *boxes, int32_t nbox, int32_t M,
+                             double dt, erpp_precision prec, int32_t self_correction,
+                             void *stream) {
+    (void)stream;
+    g_err.clear();
+    if (!out) return fail(ERPP_EINVAL, "plan pointer is NULL");
+    *out = nullptr;
+    if (!boxes || nbox < 1) return fail(ERPP_EINVAL, "need nbox >= 1 boxes (got %d)", nbox);
+    if (M < 1) return fail(ERPP_EINVAL, "M must be >= 1 (got %d)", M);
+    if (!finite_pos(dt)) return fail(ERPP_EINVAL, "dt must be finite and > 0");
+    if (prec != ERPP_F64_PLAIN && prec != ERPP_F32_FAST)
+        return fail(ERPP_EINVAL, "unknown precision %d", (int)prec);
+    if (self_correction != 0 && self_correction != 1)
+        return fail(ERPP_EINVAL, "self_correction must be 0 or 1");
+    int64_t np_total = 0;
+    std::vector<erpp::DevBox> hb(nbox);
+    for (int b = 0; b < nbox; ++b) {
+        const erpp_box &X = boxes[b];
+        erpp::DevBox &B = hb[b];
+        std::memset(&B, 0, sizeof B);
+        for (int d = 0; d < 3; ++d) {
+            if (X.n[d] < 1) return fail(ERPP_EINVAL, "box %d: n[%d]=%d < 1", b, d, X.n[d]);
+            if (!finite_pos(X.L[d])) return fail(ERPP_EGEOM, "box %d: L[%d] must be > 0", b, d);
+        }
+        if (X.np < 0) return fail(ERPP_EINVAL, "box %d: np < 0", b);
+        if (X.np > INT32_MAX) return fail(ERPP_EUNSUPPORTED, "box %d: np > 2^31-1", b);
+        if ((int64_t)X.n[0] * X.n[1] * X.n[2] > INT32_MAX)
+            return fail(ERPP_EUNSUPPORTED, "box %d: more than 2^31-1 nodes", b);
+        if (!X.u || !X.f) return fail(ERPP_EINVAL, "box %d: u or f is NULL", b);
+        if (X.np > 0 && (!X.x || !X.v || !X.ring_x || !X.ring_d || !X.tau))
+            return fail(ERPP_EINVAL, "box %d: a particle array is NULL", b);
+        if (!finite_pos(X.m_p) || !finite_pos(X.rho_f))
+            return fail(ERPP_EINVAL, "box %d: m_p and rho_f must be > 0", b);
+        if (!std::isfinite(X.nu) || X.nu < 0.0) return fail(ERPP_EINVAL, "box %d: nu < 0", b);
+        if (!finite_pos(X.sigma) || !finite_pos(X.cutoff))
+            return fail(ERPP_EGEOM, "box %d: sigma and cutoff must be > 0", b);
+        if (!std::isfinite(X.shear)) return fail(ERPP_EINVAL, "box %d: shear not finite", b);
+        const double rc = X.cutoff * X.sigma;
+        for (int d = 0; d < 3; ++d) {
+            B.n[d] = X.n[d];
+            B.L[d] = X.L[d];
+            B.dx[d] = X.L[d] / (double)X.n[d];
+            B.dxf[d] = (float)B.dx[d];
+            int32_t R = (int32_t)std::ceil(rc / B.dx[d]);
+            if (X.n[d] < 2 * R + 2)
+                return fail(ERPP_EGEOM, "box %d: N[%d]=%d < 2*R_c+2 = %d", b, d, X.n[d], 2 * R + 2);
+            stencil_range(rc, B.dx[d], B.mlo[d], B.mhi[d]);
+            if (B.mhi[d] - B.mlo[d] + 1 > 16)
+                return fail(ERPP_EUNSUPPORTED, "box %d: stencil of %d nodes in dim %d (> 16)", b,
+                            B.mhi[d] - B.mlo[d] + 1, d);
+        }
+        if (prec == ERPP_F32_FAST && (X.n[0] > 2048 || X.n[1] > 2048 || X.n[2] > 1024))
+            return fail(ERPP_EUNSUPPORTED, "box %d: grid beyond 2048 x 2048 x 1024", b);
+        B.np = X.np;
+        B.poff = np_total;
+        np_total += X.np;
+        B.dV = B.dx[0] * B.dx[1] * B.dx[2];
+        B.R2 = rc * rc;
+        B.two_s2 = 2.0 * X.sigma * X.sigma;
+        B.m_p = X.m_p;
+        B.rho_f = X.rho_f;
+        B.shear = X.shear;
+        B.s2s = X.sigma * X.sigma + 2.0 * X.nu * dt;
+        B.pref = -(dt / X.rho_f) * std::pow(2.0 * M_PI * B.s2s, -1.5);
+        B.R2f = (float)B.R2;
+        B.guard = (float)(4.0e-6 * B.R2);
+        B.cexp = (float)(1.0 / (B.two_s2 * std::log(2.0)));
+        B.s2sf = (float)B.s2s;
+        B.preff = (float)B.pref;
+        B.rhof_inv = (float)(1.0 / X.rho_f);
+        B.x = X.x;
+        B.v = X.v;
+        B.ring_x = X.ring_x;
+        B.ring_d = X.ring_d;
+        B.tau = X.tau;
+        B.u = X.u;
+        B.f = X.f;
+    }
+    if (np_total > INT32_MAX) return fail(ERPP_EUNSUPPORTED, "more than 2^31-1 particles in a plan");
+
+    erpp_plan *p = new (std::nothrow) erpp_plan();
+    if (!p) return fail(ERPP_ENOMEM, "host allocation of the plan");
+    (void)hipGetDevice(&p->device);
+    p->nbox = nbox;
+    p->M = M;
+    p->dt = dt;
+    p->prec = prec;
+    p->self_correction = self_correction;
+    p->boxes.assign(boxes, boxes + nbox);
+    p->hbox = hb;
+    p->np_total = np_total;
+    erpp::fill_box_tiles(p);
+    bool ok = alloc(&p->dbox, (size_t)nbox) == hipSuccess && alloc(&p->s.step, 1) == hipSuccess &&
+              alloc(&p->s.rank, (size_t)np_total) == hipSuccess;
+    if (ok && prec == ERPP_F32_FAST) ok = alloc(&p->s.rec, 2 * (size_t)np_total) == hipSuccess;
+    if (ok && prec == ERPP_F64_PLAIN)
+        ok = alloc(&p->s.pamp, 4 * (size_t)np_total) == hipSuccess &&
+             alloc(&p->s.pphi, 3 * (size_t)np_total) == hipSuccess &&
+             alloc(&p->s.pbase, 3 * (size_t)np_total) == hipSuccess;
+    if (!ok) {
+        free_scratch(p);
+        delete p;
+        (void)hipGetLastError();
+        return fail(ERPP_ENOMEM, "plan scratch for %lld particles", (long long)np_total);
+    }
+    erpp_status s = alloc_bins(p);
+    if (s == ERPP_OK) s = upload_boxes(p);
+    if (s == ERPP_OK && hipMemset(p->s.step, 0, sizeof(int64_t)) != hipSuccess)
+        s = fail(ERPP_EHIP, "hipMemset of the step counter");
+    if (s != ERPP_OK) {
+        free_scratch(p);
+        delete p;
+        return s;
+    }
+    *out = p;
+    return ERPP_OK;
+}
+
+erpp_status erpp_plan_set_tile(erpp_plan *p, const int32_t tile[3]) {
+    if (!p) return fail(ERPP_EINVAL, "plan is NULL");
+    erpp_status s = check_tile(tile);
+    if (s != ERPP_OK) return s;
+    for (int d = 0; d < 3; ++d) p->tile[d] = tile[d];
+    int64_t old = p->nbins_total;
+    erpp::fill_box_tiles(p);
+    drop_graph(p);
+    if (p->nbins_total != old) {
+        s = alloc_bins(p);
+        if (s != ERPP_OK) return s;
+    }
+    return upload_boxes(p);
+}
+
+erpp_status erpp_plan_get_tile(const erpp_plan *p, int32_t tile[3]) {
+    if (!p || !tile) return fail(ERPP_EINVAL, "NULL argument");
+    for (int d = 0; d < 3; ++d) tile[d] = p->tile[d];
+    return ERPP_OK;
+}
+
+erpp_status erpp_plan_bins(const erpp_plan *p, int32_t ibox, int32_t *nbin) {
+    if (!p || !nbin) return fail(ERPP_EINVAL, "NULL argument");
+    if (ibox < 0 || ibox >= p->nbox) return fail(ERPP_EINVAL, "ibox %d out of range", ibox);
+    const erpp::DevBox &B = p->hbox[ibox];
+    *nbin = B.ntile[0] * B.ntile[1] * B.ntile[2];
+    return ERPP_OK;
+}
+
+erpp_status erpp_bin(erpp_plan *p, int32_t ibox, const double *pos, int32_t *key, int32_t *perm,
+                     int32_t *bin_start, void *stream) {
+    if (!p) return fail(ERPP_EINVAL, "plan is NULL");
+    if (ibox < 0 || ibox >= p->nbox) return fail(ERPP_EINVAL, "ibox %d out of range", ibox);
+    if (!bin_start) return fail(ERPP_EINVAL, "bin_start is NULL");
+    if (p->hbox[ibox].np > 0 && (!pos || !key || !perm))
+        return fail(ERPP_EINVAL, "pos, key or perm is NULL");
+    hipError_t e = erpp::fast_bin_positions(p, ibox, pos, key, perm, bin_start, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "erpp_bin launch");
+    return ERPP_OK;
+}
+
+erpp_status erpp_scatter(erpp_plan *p, int64_t step, void *stream) {
+    if (!p) return fail(ERPP_EINVAL, "plan is NULL");
+    if (step < 0) return fail(ERPP_EINVAL, "step < 0");
+    hipStream_t st = as_stream(stream);
+    hipError_t e = erpp::set_step(p, step, st);
+    if (e != hipSuccess) return hip_fail(e, "set_step");
+    return run_stages(p, st, false);
+}
+
+erpp_status erpp_gather(erpp_plan *p, double *u_p, void *stream) {
+    if (!p) return fail(ERPP_EINVAL, "plan is NULL");
+    if (!u_p && p->np_total > 0) return fail(ERPP_EINVAL, "u_p is NULL");
+    hipError_t e = erpp::fast_gather(p, u_p, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "erpp_gather launch");
+    return ERPP_OK;
+}
+
+erpp_status erpp_step(erpp_plan *p, int64_t step, void *stream) {
+    if (!p) return fail(ERPP_EINVAL, "plan is NULL");
+    if (step < 0) return fail(ERPP_EINVAL, "step < 0");
+    hipStream_t st = as_stream(stream);
+    hipError_t e = erpp::set_step(p, step, st);
+    if (e != hipSuccess) return hip_fail(e, "set_step");
+    return run_stages(p, st, true);
+}
+
+erpp_status erpp_run(erpp_plan *p, int64_t step0, int64_t nsteps, int32_t use_graph,
+                     void *stream) {
+    if (!p) return fail(ERPP_EINVAL, "plan is NULL");
+    if (step0 < 0 || nsteps < 0) return fail(ERPP_EINVAL, "step0 and nsteps must be >= 0");
+    hipStream_t st = as_stream(stream);
+    if (!use_graph) {
+        for (int64_t i = 0; i < nsteps; ++i) {
+            erpp_status s = erpp_step(p, step0 + i, stream);
+            if (s != ERPP_OK) return s;
+        }
+        return ERPP_OK;
+    }
+    if (!p->graph_exec) {
+        hipStream_t cap;
+        HIP_OR_RETURN(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            (void)hipStreamDestroy(cap);
+            return hip_fail(e, "hipStreamBeginCapture");
+        }
+        erpp_status s = run_stages(p, cap, true);
+        hipError_t e2 = erpp::advance_step(p, cap);
+        hipGraph_t g = nullptr;
+        hipError_t e3 = hipStreamEndCapture(cap, &g);
+        (void)hipStreamDestroy(cap);
+        if (s != ERPP_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e2 != hipSuccess || e3 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(e2 != hipSuccess ? e2 : e3, "graph capture");
+        }
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        p->graph = g;
+        p->graph_exec = ex;
+    }
+    HIP_OR_RETURN(erpp::set_step(p, step0, st));
+    for (int64_t i = 0; i < nsteps; ++i) HIP_OR_RETURN(hipGraphLaunch(p->graph_exec, st));
+    return ERPP_OK;
+}
+
+erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
+    if (!p) return fail(ERPP_EINVAL, "plan is NULL");
+    if (p->prec != ERPP_F32_FAST) return ERPP_OK;
+    hipStream_t st = as_stream(stream);
+    // geometry key
+    std::ostringstream key;
+    key << "v1 M" << p->M << " nbox" << p->nbox;
+    for (const auto &B : p->hbox)
+        key << " " << B.n[0] << "x" << B.n[1] << "x" << B.n[2] << ":" << B.np << ":" << B.mlo[0]
+            << "," << B.mhi[0];
+    const std::string k = key.str();
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            size_t bar = line.rfind('|');
+            if (bar == std::string::npos || line.substr(0, bar) != k) continue;
+            int32_t t[3];
+            if (std::sscanf(line.c_str() + bar + 1, "%d %d %d", &t[0], &t[1], &t[2]) == 3 &&
+                check_tile(t) == ERPP_OK)
+                return erpp_plan_set_tile(p, t);
+        }
+    }
+    static const int32_t cand[][3] = {{8, 8, 8},   {16, 8, 8},   {16, 16, 8}, {16, 16, 16},
+                                      {32, 8, 8},  {32, 16, 8},  {32, 16, 16}, {32, 32, 8},
+                                      {64, 8, 8},  {64, 16, 8},  {16, 16, 32}, {32, 8, 16}};
+    const int ncand = (int)(sizeof cand / sizeof cand[0]);
+    int32_t best[3] = {p->tile[0], p->tile[1], p->tile[2]};
+    float best_ms = 1e30f;
+    hipEvent_t a, b;
+    HIP_OR_RETURN(hipEventCreate(&a));
+    HIP_OR_RETURN(hipEventCreate(&b));
+    // the scatter reads ring level n-M; use the step following the last one run
+    int64_t n = 0;
+    HIP_OR_RETURN(hipMemcpy(&n, p->s.step, sizeof n, hipMemcpyDeviceToHost));
+    if (n < p->M) n = p->M;
+    erpp_status status = ERPP_OK;
+    for (int c = 0; c < ncand && status == ERPP_OK; ++c) {
+        if (check_tile(cand[c]) != ERPP_OK) continue;
+        status = erpp_plan_set_tile(p, cand[c]);
+        if (status != ERPP_OK) break;
+        status = erpp_scatter(p, n, stream);   // warm-up
+        if (status != ERPP_OK) break;
+        (void)hipEventRecord(a, st);
+        const int reps = 3;
+        for (int r = 0; r < reps && status == ERPP_OK; ++r) status = erpp_scatter(p, n, stream);
+        (void)hipEventRecord(b, st);
+        if (hipEventSynchronize(b) != hipSuccess) {
+            status = fail(ERPP_EHIP, "autotuner synchronisation");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        if (ms < best_ms) {
+            best_ms = ms;
+            std::memcpy(best, cand[c], sizeof best);
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    // leave the step counter where it was
+    (void)erpp::set_step(p, n, st);
+    if (status != ERPP_OK) return status;
+    status = erpp_plan_set_tile(p, best);
+    if (status == ERPP_OK && cache_path) {
+        std::ofstream o(cache_path, std::ios::app);
+        if (o) o << k << "|" << best[0] << " " << best[1] << " " << best[2] << "\n";
+    }
+    return status;
+}
+
+erpp_status erpp_stage_times(erpp_plan *p, int64_t step0, int64_t nsteps, double ms[5],
+                             void *stream) {
+    if (!p || !ms) return fail(ERPP_EINVAL, "NULL argument");
+    if (step0 < 0 || nsteps < 1) return fail(ERPP_EINVAL, "need step0 >= 0 and nsteps >= 1");
+    hipStream_t st = as_stream(stream);
+    hipEvent_t ev[6];
+    for (int k = 0; k < 6; ++k) HIP_OR_RETURN(hipEventCreate(&ev[k]));
+    double acc[5] = {0, 0, 0, 0, 0};
+    erpp_status status = ERPP_OK;
+    for (int64_t i = 0; i < nsteps && status == ERPP_OK; ++i) {
+        hipError_t e = erpp::set_step(p, step0 + i, st);
+        (void)hipEventRecord(ev[0], st);
+        for (int k = 0; k < 5 && e == hipSuccess; ++k) {
+            e = p->prec == ERPP_F32_FAST ? erpp::fast_stage(p, k, st) : erpp::plain_stage(p, k, st);
+            if (e == hipSuccess) e = hipEventRecord(ev[k + 1], st);
+        }
+        if (e == hipSuccess) e = hipEventSynchronize(ev[5]);
+        if (e != hipSuccess) {
+            status = hip_fail(e, "erpp_stage_times");
+            break;
+        }
+        for (int k = 0; k < 5; ++k) {
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+            acc[k] += t;
+        }
+    }
+    for (int k = 0; k < 6; ++k) (void)hipEventDestroy(ev[k]);
+    if (status != ERPP_OK) return status;
+    for (int k = 0; k < 5; ++k) ms[k] = acc[k] / (double)nsteps;
+    return ERPP_OK;
+}
+
+void erpp_plan_destroy(erpp_plan *p) {
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    drop_graph(p);
+    free_scratch(p);
+    delete p;
+}
+
+}  // extern "C"

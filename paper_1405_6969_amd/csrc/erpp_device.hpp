@@ -1,0 +1,275 @@
+// erpp_device.hpp -- device helpers of the ERPP coupling step (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "erpp_internal.hpp"
+
+namespace erpp {
+
+// Box of a block from the box-aligned block offsets (uniform per block).
+template <typename F>
+__device__ __forceinline__ int box_of_block(const DevBox *__restrict__ B, int nbox,
+                                            int64_t blk, F key) {
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (key(B[mid]) <= blk) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- FP64 cell --
+// Periodic wrap into [0, L) and cell index / offset of a coordinate with nodes at
+// i*dx.  Every operation rounded as written (same arithmetic as the reference
+// definition: y = x - L floor(x/L); s = y/dx; b = min(floor(s), N-1); phi = s - b).
+__device__ __forceinline__ double wrap_coord(double x, double L) {
+#pragma clang fp contract(off)
+    double y = x - L * floor(x / L);
+    if (y >= L) y -= L;
+    if (y < 0.0) y = 0.0;
+    return y;
+}
+
+__device__ __forceinline__ void cell_of(double x, double L, double dx, int N, int &b,
+                                        double &phi) {
+#pragma clang fp contract(off)
+    double xh = wrap_coord(x, L);
+    double s = xh / dx;
+    double fb = floor(s);
+    int i = (int)fb;
+    if (i > N - 1) i = N - 1;
+    if (i < 0) i = 0;
+    b = i;
+    phi = s - (double)i;
+}
+
+// Sphere membership of stencil node (mx,my,mz) in FP64, rounded exactly like the
+// definition: d = (m - phi) dx per dimension, r2 = dx^2 + dy^2 + dz^2 <= R2.
+__device__ __noinline__ bool inside64(int mx, int my, int mz, double phx, double phy,
+                                      double phz, const DevBox &B) {
+#pragma clang fp contract(off)
+    double ddx = ((double)mx - phx) * B.dx[0];
+    double dy = ((double)my - phy) * B.dx[1];
+    double dz = ((double)mz - phz) * B.dx[2];
+    double r2 = ddx * ddx + dy * dy + dz * dz;
+    return r2 <= B.R2;
+}
+
+// Sphere membership decided in FP64 for a particle whose FP32 test fell inside
+// the guard band: re-read its delayed position from the ring (rare path).
+__device__ __noinline__ bool inside_exact(const DevBox *__restrict__ Bp, int64_t slot, int pid,
+                                          int mx, int my, int mz) {
+    const DevBox &B = *Bp;
+    const int64_t np = B.np;
+    const double *X = B.ring_x + slot * 3 * np;
+    int b;
+    double phx, phy, phz;
+    cell_of(X[pid], B.L[0], B.dx[0], B.n[0], b, phx);
+    cell_of(X[np + pid], B.L[1], B.dx[1], B.n[1], b, phy);
+    cell_of(X[2 * np + pid], B.L[2], B.dx[2], B.n[2], b, phz);
+    return inside64(mx, my, mz, phx, phy, phz, B);
+}
+
+// -------------------------------------------------------------- FP32 kernel --
+// 1-D factor of the raw Gaussian: exp2(-t^2 cexp), t = (m - phi) dx.
+__device__ __forceinline__ float g1(int m, float phi, float dxf, float cexp) {
+    float t = ((float)m - phi) * dxf;
+    return exp2f(-(t * t) * cexp);
+}
+
+__device__ __forceinline__ float d1(int m, float phi, float dxf) {
+    float t = ((float)m - phi) * dxf;
+    return t;
+}
+
+// Sphere decision for node mx of row (my, mz) in FP32 (ryz = dy^2 + dz^2 of the
+// row, fused), with the FP64 decision inside the guard band around R2.
+__device__ __forceinline__ bool inside32(int mx, float phx, float ryz, const DevBox &B,
+                                         const DevBox *Bp, int64_t slot, int pid, int my,
+                                         int mz) {
+    float t = ((float)mx - phx) * B.dxf[0];
+    float d2 = fmaf(t, t, ryz);
+    if (d2 < B.R2f - B.guard) return true;
+    if (d2 > B.R2f + B.guard) return false;
+    return inside_exact(Bp, slot, pid, mx, my, mz);
+}
+
+// Contiguous range [lo, hi] of x offsets of row (my, mz) inside the sphere,
+// within [mlo, mhi].  lo > hi when the row is empty.  A square-root estimate is
+// trusted when it is far from an integer and the row is not tiny; otherwise the
+// ends are settled node by node with inside32 (membership is monotone in |mx -
+// phi| along a row).  Deterministic in its inputs, so every kernel that calls it
+// sees the same node set.
+__device__ __forceinline__ void row_range(float phx, float ryz, const DevBox &B,
+                                          const DevBox *Bp, int64_t slot, int pid, int my,
+                                          int mz, int &lo, int &hi) {
+    const int mlo = B.mlo[0], mhi = B.mhi[0];
+    float rem = B.R2f - ryz;
+    if (rem < -B.guard) { lo = 1; hi = 0; return; }
+    float s = sqrtf(fmaxf(rem, 0.0f)) / B.dxf[0];
+    float tl = phx - s, th = phx + s;
+    float cl = ceilf(tl), fh = floorf(th);
+    const float eps = 1.0e-4f;
+    bool trust = (s >= 0.5f) && (cl - tl > eps) && (tl - (cl - 1.0f) > eps) &&
+                 (th - fh > eps) && ((fh + 1.0f) - th > eps);
+    int l = (int)cl, h = (int)fh;
+    if (!trust) {
+        if (l < mlo) l = mlo;
+        if (h > mhi) h = mhi;
+        while (l - 1 >= mlo && inside32(l - 1, phx, ryz, B, Bp, slot, pid, my, mz)) --l;
+        while (l <= h && !inside32(l, phx, ryz, B, Bp, slot, pid, my, mz)) ++l;
+        while (h + 1 <= mhi && inside32(h + 1, phx, ryz, B, Bp, slot, pid, my, mz)) ++h;
+        while (h >= l && !inside32(h, phx, ryz, B, Bp, slot, pid, my, mz)) --h;
+    }
+    if (l < mlo) l = mlo;
+    if (h > mhi) h = mhi;
+    lo = l;
+    hi = h;
+}
+
+// ---------------------------------------------------------- self-disturbance --
+// App. E closed form (with the -dt/rho_f prefactor), FP32.  r = x - X' (min
+// image), D' the drag injected one step earlier.  Series for eta < 0.3.
+__device__ __forceinline__ void self_disturbance32(float rx, float ry, float rz, float Dx,
+                                                   float Dy, float Dz, float s2, float pref,
+                                                   float &vx, float &vy, float &vz) {
+    float rr = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
+    float eta2 = rr / (2.0f * s2);
+    float e = expf(-eta2);
+    float Dr = fmaf(Dx, rx, fmaf(Dy, ry, Dz * rz));
+    float F, Hr;
+    if (eta2 < 0.09f) {
+        // F = sum_j (-1)^j eta^2j/(j!(2j+3)),  (e - 3F)/eta^2 = sum_{j>=1} 2j (-1)^j eta^2(j-1)/(j!(2j+3))
+        float t = 1.0f, q = -1.0f;
+        F = 0.0f;
+        Hr = 0.0f;
+#pragma unroll
+        for (int j = 0; j <= 5; ++j) {
+            F = fmaf(t, 1.0f / (2.0f * j + 3.0f), F);
+            t *= -eta2 / (float)(j + 1);
+        }
+#pragma unroll
+        for (int j = 1; j <= 5; ++j) {
+            Hr = fmaf((2.0f * j) / (2.0f * j + 3.0f), q, Hr);
+            q *= -eta2 / (float)(j + 1);
+        }
+        Hr /= 2.0f * s2;
+    } else {
+        float eta = sqrtf(eta2);
+        float fe = 0.88622692545275801f * erff(eta) - eta * e;
+        F = fe / (2.0f * eta * eta2);
+        Hr = (e - 3.0f * F) / rr;
+    }
+    float a = e - F;
+    float b = Dr * Hr;
+    vx = pref * (a * Dx - b * rx);
+    vy = pref * (a * Dy - b * ry);
+    vz = pref * (a * Dz - b * rz);
+}
+
+// FP64 version (plain path), series through j = 8 below eta = 0.3.
+__device__ __forceinline__ void self_disturbance64(const double r[3], const double D[3],
+                                                   double s2, double pref, double v[3]) {
+    double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double eta2 = rr / (2.0 * s2);
+    double eta = sqrt(eta2);
+    double e = exp(-eta2);
+    double Dr = D[0] * r[0] + D[1] * r[1] + D[2] * r[2];
+    double F, Hr;
+    if (eta < 0.3) {
+        double t = 1.0, q = -1.0;
+        F = 0.0;
+        Hr = 0.0;
+        for (int j = 0; j <= 8; ++j) {
+            F += t / (2.0 * j + 3.0);
+            t *= -eta2 / (double)(j + 1);
+        }
+        for (int j = 1; j <= 8; ++j) {
+            Hr += (2.0 * j) * q / (2.0 * j + 3.0);
+            q *= -eta2 / (double)(j + 1);
+        }
+        Hr /= 2.0 * s2;
+    } else {
+        double fe = 0.88622692545275801365 * erf(eta) - eta * e;
+        F = fe / (2.0 * eta * eta2);
+        Hr = (e - 3.0 * F) / rr;
+    }
+    for (int c = 0; c < 3; ++c) v[c] = pref * ((e - F) * D[c] - Dr * r[c] * Hr);
+}
+
+// Trilinear interpolation of a [3][Nz][Ny][Nx] field at x (FP64 weights).
+template <typename T>
+__device__ __forceinline__ void trilinear(const DevBox &B, const T *__restrict__ u,
+                                          const double xp[3], double out[3]) {
+    int b[3];
+    double ph[3];
+    for (int d = 0; d < 3; ++d) cell_of(xp[d], B.L[d], B.dx[d], B.n[d], b[d], ph[d]);
+    const int64_t Nx = B.n[0], Ny = B.n[1], Nz = B.n[2];
+    const int64_t ng = Nx * Ny * Nz;
+    int64_t i0 = b[0], i1 = (b[0] + 1 == B.n[0]) ? 0 : b[0] + 1;
+    int64_t j0 = b[1], j1 = (b[1] + 1 == B.n[1]) ? 0 : b[1] + 1;
+    int64_t k0 = b[2], k1 = (b[2] + 1 == B.n[2]) ? 0 : b[2] + 1;
+    double wx[2] = {1.0 - ph[0], ph[0]};
+    double wy[2] = {1.0 - ph[1], ph[1]};
+    double wz[2] = {1.0 - ph[2], ph[2]};
+    int64_t ii[2] = {i0, i1}, jj[2] = {j0 * Nx, j1 * Nx}, kk[2] = {k0 * Nx * Ny, k1 * Nx * Ny};
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+        for (int c1 = 0; c1 < 2; ++c1)
+#pragma unroll
+            for (int c0 = 0; c0 < 2; ++c0) {
+                double w = wx[c0] * wy[c1] * wz[c2];
+                int64_t node = kk[c2] + jj[c1] + ii[c0];
+                acc0 += w * (double)u[node];
+                acc1 += w * (double)u[ng + node];
+                acc2 += w * (double)u[2 * ng + node];
+            }
+    if (B.shear != 0.0) {
+        double yh = wrap_coord(xp[1], B.L[1]);
+        acc0 += B.shear * (yh - 0.5 * B.L[1]);
+    }
+    out[0] = acc0;
+    out[1] = acc1;
+    out[2] = acc2;
+}
+
+// Drag, history write, explicit Euler and periodic wrap (Lees-Edwards velocity
+// jump in y when a mean shear is present).  FP64.
+__device__ __forceinline__ void update_particle(const DevBox &B, int64_t p, double dt,
+                                                const double xp[3], const double up[3],
+                                                const double vs[3], double *hx, double *hdD,
+                                                float *hdF) {
+#pragma clang fp contract(off)
+    const int64_t np = B.np;
+    double t = (double)B.tau[p];
+    double D[3], xn[3], vn[3];
+    for (int d = 0; d < 3; ++d) {
+        double ut = up[d] - vs[d];
+        double vd = B.v[d * np + p];
+        D[d] = B.m_p * (ut - vd) / t;
+        xn[d] = xp[d] + dt * vd;
+        vn[d] = vd;
+    }
+    for (int d = 0; d < 3; ++d) {
+        hx[d * np + p] = xp[d];
+        if (hdD) hdD[d * np + p] = D[d];
+        if (hdF) hdF[d * np + p] = (float)D[d];
+        vn[d] += dt * D[d] / B.m_p;
+    }
+    for (int d = 0; d < 3; ++d) {
+        double L = B.L[d];
+        double fl = floor(xn[d] / L);
+        double w = xn[d] - L * fl;
+        int64_t k = (int64_t)fl;
+        if (w >= L) { w -= L; k += 1; }
+        if (w < 0.0) w = 0.0;
+        B.x[d * np + p] = w;
+        if (d == 1 && B.shear != 0.0 && k != 0) vn[0] -= (double)k * B.shear * L;
+    }
+    for (int d = 0; d < 3; ++d) B.v[d * np + p] = vn[d];
+}
+
+}  // namespace erpp

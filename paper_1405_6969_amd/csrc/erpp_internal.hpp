@@ -1,0 +1,114 @@
+// erpp_internal.hpp -- plan and per-box descriptors shared by the host API and
+// the kernels of the MI355X ERPP coupling step.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/erpp.h"
+
+namespace erpp {
+
+constexpr int kMaxTileDim = 64;
+constexpr int kMaxTileVol = 8192;
+constexpr int kBlock = 256;          // threads per block of particle kernels
+constexpr int kScatterBlock = 512;   // threads per block of the tiled scatter
+
+// Everything a kernel needs to know about one box; lives in device memory as
+// an array indexed by box.  Plain old data.
+struct DevBox {
+    int32_t n[3];        // nodes
+    int32_t mlo[3];      // stencil offsets m in [mlo, mhi] around the base cell
+    int32_t mhi[3];
+    int32_t T[3];        // scatter tile (nodes) of this box, clipped
+    int32_t ntile[3];    // tiles per dimension
+    int32_t pad0;
+    int64_t np;          // particles
+    int64_t poff;        // first particle in the concatenated particle space
+    int64_t bin_off;     // first bin (tile) of this box in the global bin array
+    int64_t blk_p;       // first block of this box in particle launches
+    int64_t blk_t;       // first block of this box in tile launches
+    int64_t blk_r;       // first block of this box in (particle, row) launches
+    int64_t rows;        // stencil rows (my, mz) per particle
+    double L[3];
+    double dx[3];        // L / N
+    double dV;
+    double R2;           // (cutoff * sigma)^2, FP64 sphere threshold
+    double two_s2;       // 2 sigma^2
+    double m_p, rho_f, shear;
+    double s2s;          // sigma_s^2 = sigma^2 + 2 nu dt  (self-disturbance width)
+    double pref;         // -(dt/rho_f) (2 pi sigma_s^2)^(-3/2)
+    float dxf[3];
+    float R2f;           // FP32 sphere threshold
+    float guard;         // |d2 - R2f| <= guard: decide in FP64
+    float cexp;          // 1 / (2 sigma^2 ln 2): raw weight = exp2(-d2 cexp)
+    float s2sf, preff;
+    float rhof_inv;
+    float pad1;
+    double *x, *v, *ring_x;
+    void *ring_d;
+    const float *tau;
+    const void *u;
+    void *f;
+};
+
+struct Scratch {
+    // ERPP_F32_FAST
+    int32_t *count = nullptr;    // [nbins_total]   per-step histogram (kept zero at rest)
+    int32_t *start = nullptr;    // [nbins_total+1] exclusive scan
+    int32_t *rank = nullptr;     // [np_total]      rank of a particle inside its bin
+    float4 *rec = nullptr;       // [2*np_total]    tile-sorted injection records
+    uint32_t *binmax = nullptr;  // [nbins_total]   largest |amplitude| per bin (float bits)
+    // ERPP_F64_PLAIN
+    double *pamp = nullptr;      // [4][np_total] -D/rho_f (3 components) and Z
+    double *pphi = nullptr;      // [3][np_total] offsets inside the base cell
+    int32_t *pbase = nullptr;    // [3][np_total] base cell
+    // both
+    int64_t *step = nullptr;     // device copy of the step index
+};
+
+}  // namespace erpp
+
+struct erpp_plan {
+    int device = 0;
+    int32_t nbox = 0;
+    int32_t M = 1;
+    double dt = 0;
+    erpp_precision prec = ERPP_F32_FAST;
+    int32_t self_correction = 1;
+    int32_t tile[3] = {16, 16, 16};
+    std::vector<erpp_box> boxes;
+    std::vector<erpp::DevBox> hbox;
+    erpp::DevBox *dbox = nullptr;
+    int64_t np_total = 0;
+    int64_t nbins_total = 0;
+    int64_t pblocks = 0;         // blocks of particle launches (box aligned)
+    int64_t tblocks = 0;         // blocks of tile launches
+    int64_t pblocks_rows = 0;    // plain scatter: blocks over (particle,row)
+    erpp::Scratch s;
+    size_t lds_bytes = 0;
+    // graph of one step (step index read from s.step)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+};
+
+namespace erpp {
+// kernel launchers (each returns hipSuccess or the launch error)
+hipError_t fast_stage(erpp_plan *p, int k, hipStream_t st);      // k = 0 bin .. 4 update
+hipError_t plain_stage(erpp_plan *p, int k, hipStream_t st);
+hipError_t fast_scatter_stages(erpp_plan *p, hipStream_t st);   // bin, scan, eval, scatter
+hipError_t fast_update_stage(erpp_plan *p, hipStream_t st);     // gather, self term, update
+hipError_t fast_gather(erpp_plan *p, double *u_p, hipStream_t st);
+hipError_t fast_bin_positions(erpp_plan *p, int ibox, const double *pos, int32_t *key,
+                              int32_t *perm, int32_t *bin_start, hipStream_t st);
+hipError_t plain_scatter_stages(erpp_plan *p, hipStream_t st);
+hipError_t plain_update_stage(erpp_plan *p, hipStream_t st);
+hipError_t set_step(erpp_plan *p, int64_t n, hipStream_t st);
+hipError_t advance_step(erpp_plan *p, hipStream_t st);
+void fill_box_tiles(erpp_plan *p);          // recompute tiles/bins/blocks on host
+size_t scatter_lds_bytes(const int32_t tile[3]);   // int32 tile + staged visits
+hipError_t fast_prepare_lds(size_t bytes);         // opt the scatter into > 64 KB LDS
+constexpr size_t kMaxScatterLds = 150 * 1024;
+}  // namespace erpp

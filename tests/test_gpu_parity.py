@@ -1,0 +1,310 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.
+
+Bars (written here): ERPP_F32_FAST rel-L2(f) <= 1e-5 per step and
+rel-L2(v) <= 1e-6 at the end of a run; ERPP_F64_PLAIN <= 1e-12 and <= 1e-13.
+Bin keys are compared exactly.  Step 0..M-1 forcing must be exactly zero.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from helpers import oracle_run, periodic_diff, rel_l2, tolerances, upload
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+erpp = pytest.importorskip("paper_1405_6969_amd")
+PRECS = [erpp.F32_FAST, erpp.F64_PLAIN]
+
+
+def _cuda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _fill_level(db, slot, X, D):
+    db.ring_x[slot].copy_(torch.as_tensor(X, dtype=torch.float64))
+    db.ring_d[slot].copy_(torch.as_tensor(D, dtype=db.ring_d.dtype))
+
+
+# -------------------------------------------------------------- scatter ----
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("shape,np_,sigma_dx,tile,placement", [
+    ((32, 32, 32), 1000, 1.5, (16, 16, 16), "uniform"),
+    ((40, 36, 44), 2500, 1.5, (16, 16, 16), "clustered"),    # ragged tiles
+    ((48, 40, 36), 1800, 2.0, (16, 8, 8), "clustered"),      # sigma = 2 dx, R_c = 6
+    ((12, 13, 14), 60, 1.5, (16, 16, 16), "uniform"),        # tiny: tiles clipped to 2..4
+    ((64, 24, 20), 3000, 1.5, (32, 8, 8), "uniform"),
+])
+def test_scatter_matches_oracle(prec, shape, np_, sigma_dx, tile, placement):
+    _cuda()
+    spec = workloads.BoxSpec(n=shape, L=tuple(2 * math.pi * s / shape[0] for s in shape),
+                             np_=np_, placement=placement, sigma_dx=sigma_dx, blob_radius_dx=3.0,
+                             n_blobs=5, kmax=6.0, seed=101 + shape[0] + np_)
+    box = workloads.make_box(spec)
+    M = 3
+    db = upload(box, M, prec)
+    rng = np.random.default_rng(7 + np_)
+    D = rng.normal(size=(3, np_))
+    if prec == erpp.F32_FAST:
+        D = D.astype(np.float32).astype(np.float64)
+    n = 7
+    slot = (n - M) % (M + 1)
+    _fill_level(db, slot, box.x, D)
+    with erpp.Plan([db], M, 1e-3, precision=prec) as plan:
+        if prec == erpp.F32_FAST:
+            plan.set_tile(tile)
+        plan.scatter(n)
+        fg = db.f.double().cpu().numpy()
+    P = oracle.params_for_box(box, M, 1e-3)
+    fo = oracle.deposit(P, box.x, D)
+    tol_f, _ = tolerances(prec)
+    assert rel_l2(fg, fo) <= tol_f, rel_l2(fg, fo)
+    # momentum balance of the GPU forcing alone
+    dV = np.prod(box.dx)
+    lhs = spec.rho_f * dV * fg.reshape(3, -1).sum(axis=1)
+    assert np.allclose(lhs, -D.sum(axis=1), rtol=0, atol=(1e-6 if prec else 1e-12) * np.abs(D).sum())
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_scatter_before_delay_is_zero(prec):
+    _cuda()
+    box = workloads.tiny_box(5, n=(32, 32, 32), np_=100)
+    M = 4
+    db = upload(box, M, prec)
+    db.f.fill_(123.0)
+    with erpp.Plan([db], M, 1e-3, precision=prec) as plan:
+        for n in range(M):
+            db.f.fill_(123.0)
+            plan.scatter(n)
+            assert not torch.any(db.f != 0).item()
+
+
+def test_scatter_fp64_fallback_band():
+    """Particles placed so that stencil nodes sit within a few ulps of the
+    3-sigma sphere: the FP32 path must take the same node set as FP64."""
+    _cuda()
+    n = 32
+    L = 2 * math.pi
+    dx = L / n
+    rng = np.random.default_rng(3)
+    # offsets such that (m - phi)^2 dx^2 + ... hits R^2 = (4.5 dx)^2 exactly-ish:
+    # a node at (4.5 - phi_x, 0, 0): phi_x = 0.5 puts node m=5? d = 4.5 dx
+    X = np.stack([(np.arange(64) % 16 + 0.5) * dx * 1.0, (np.arange(64) // 16 + 7.0) * dx,
+                  np.full(64, 11.0 * dx)])
+    X[0] += rng.uniform(-1e-13, 1e-13, 64)
+    box = workloads.tiny_box(9, n=(n, n, n), np_=64, L=(L, L, L))
+    box.x = X
+    M = 2
+    D = rng.normal(size=(3, 64)).astype(np.float32).astype(np.float64)
+    db = upload(box, M, erpp.F32_FAST)
+    _fill_level(db, (5 - M) % (M + 1), X, D)
+    with erpp.Plan([db], M, 1e-3, precision=erpp.F32_FAST) as plan:
+        plan.scatter(5)
+        fg = db.f.double().cpu().numpy()
+    P = oracle.params_for_box(box, M, 1e-3)
+    fo = oracle.deposit(P, X, D)
+    assert np.array_equal(fg != 0, fo != 0)
+    assert rel_l2(fg, fo) <= 1e-5
+
+
+# --------------------------------------------------------------- gather ----
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_gather_matches_oracle(prec):
+    _cuda()
+    spec = workloads.BoxSpec(n=(40, 24, 28), L=(4.0, 2.4, 2.8), np_=5000, shear=0.8,
+                             kmin=1.0, kmax=8.0, seed=77)
+    box = workloads.make_box(spec)
+    box.x[:, :4] = np.array([[0.0, 4.0 - 1e-15, 3.95, 0.1], [0.0, 2.4 - 1e-15, 0.05, 2.35],
+                             [0.0, 2.8 - 1e-15, 1.0, 2.75]])
+    db = upload(box, 2, prec)
+    with erpp.Plan([db], 2, 1e-3, precision=prec) as plan:
+        ug = plan.gather()[0].cpu().numpy()
+    P = oracle.params_for_box(box, 2, 1e-3)
+    from helpers import carrier_for
+    uo = oracle.gather(P, carrier_for(box, prec), box.x)
+    tol = 1e-13 if prec == erpp.F64_PLAIN else 1e-12
+    assert np.max(np.abs(ug - uo)) <= tol * np.max(np.abs(uo))
+
+
+# ------------------------------------------------------------------ bin ----
+
+@pytest.mark.parametrize("shape,tile", [((32, 32, 32), (16, 16, 16)), ((40, 36, 44), (16, 8, 16)),
+                                        ((256, 128, 128), (32, 16, 8))])
+def test_bin_keys_exact_and_grouping(shape, tile):
+    _cuda()
+    spec = workloads.BoxSpec(n=shape, L=(0.05 * shape[0], 0.05 * shape[1], 0.05 * shape[2]),
+                             np_=20000, placement="clustered", n_blobs=30, carrier="zero",
+                             seed=55)
+    box = workloads.make_box(spec)
+    box.x[:, :3] = np.array([[0.0, spec.L[0] * (1 - 1e-17), spec.L[0] - 1e-12],
+                             [0.0, 1e-300, spec.L[1] - 1e-12], [spec.L[2] * (1 - 1e-17), 0.0, 0.0]])
+    db = upload(box, 2, erpp.F32_FAST)
+    with erpp.Plan([db], 2, 1e-3) as plan:
+        plan.set_tile(tile)
+        key, perm, start = plan.bin(0, db.x)
+        key, perm, start = key.cpu().numpy(), perm.cpu().numpy(), start.cpu().numpy()
+        nb = plan.nbins(0)
+    P = oracle.params_for_box(box, 2, 1e-3)
+    ko, _, _ = oracle.bin_cells(P, box.x)
+    assert np.array_equal(key, ko)
+    assert start[0] == 0 and start[-1] == box.np_ and np.all(np.diff(start) >= 0)
+    assert np.array_equal(np.sort(perm), np.arange(box.np_))
+    Nx, Ny, Nz = shape
+    T = [min(tile[d], shape[d] - 10) for d in range(3)]
+    nt = [-(-shape[d] // T[d]) for d in range(3)]
+    assert nb == nt[0] * nt[1] * nt[2]
+    i, j, k = key % Nx, (key // Nx) % Ny, key // (Nx * Ny)
+    tid = ((k // T[2]) * nt[1] + j // T[1]) * nt[0] + i // T[0]
+    for b in range(nb):
+        assert np.all(tid[perm[start[b]:start[b + 1]]] == b)
+
+
+# ----------------------------------------------------------------- step ----
+
+def _run_parity(boxes, M, dt, steps, prec, s=1, tile=None, graph=False, every=1):
+    dbs = [upload(b, M, prec) for b in boxes]
+    runs = [oracle_run(b, M, dt, s, prec) for b in boxes]
+    tol_f, tol_v = tolerances(prec)
+    worst = 0.0
+    with erpp.Plan(dbs, M, dt, precision=prec, self_correction=s) as plan:
+        if tile is not None and prec == erpp.F32_FAST:
+            plan.set_tile(tile)
+        for n in range(steps):
+            if graph:
+                plan.run(n, 1, graph=True)
+            else:
+                plan.step(n)
+            for db, run in zip(dbs, runs):
+                fo, Do = run.step(want_f=(n % every == 0))
+                if fo is None:
+                    continue
+                fg = db.f.double().cpu().numpy()
+                if n < M:
+                    assert not np.any(fg), "forcing before the delay"
+                    continue
+                e = rel_l2(fg, fo)
+                worst = max(worst, e)
+                assert e <= tol_f, (n, e)
+                Dg = db.ring_d[n % (M + 1)].double().cpu().numpy()
+                assert rel_l2(Dg, Do) <= (1e-6 if prec == erpp.F32_FAST else 1e-12), n
+        torch.cuda.synchronize()
+    for db, run, b in zip(dbs, runs, boxes):
+        ev = rel_l2(db.v.cpu().numpy(), run.v)
+        assert ev <= tol_v, ev
+        dxp = periodic_diff(db.x.cpu().numpy(), run.x, b.L)
+        if dxp.size:
+            assert np.max(np.abs(dxp)) <= (1e-9 if prec == erpp.F32_FAST else 1e-12)
+    return worst
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_step_config1(prec):
+    _cuda()
+    w = workloads.config(1)
+    _run_parity(workloads.make_boxes(w), w.M, w.dt, w.steps, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_step_config2_reduced(prec):
+    """Workload 2 (128^3 k^-5/3, uniform) with 2e4 particles and M+6 steps."""
+    _cuda()
+    w = workloads.config(2, np_=20000)
+    _run_parity(workloads.make_boxes(w), w.M, w.dt, w.M + 6, prec, every=3)
+
+
+def test_step_self_correction_off():
+    _cuda()
+    w = workloads.config(1, np_=500)
+    _run_parity(workloads.make_boxes(w), w.M, w.dt, 9, erpp.F32_FAST, s=0)
+
+
+def test_step_shear_and_lees_edwards():
+    """Mean shear with particles crossing the y boundary."""
+    _cuda()
+    spec = workloads.BoxSpec(n=(48, 32, 32), L=(3.0, 2.0, 2.0), np_=3000, urms=0.3, shear=40.0,
+                             placement="clustered", n_blobs=8, tau=(0.02, 0.1, 0.5),
+                             kmin=2.0, kmax=10.0, seed=303)
+    box = workloads.make_box(spec)
+    box.x[1, :200] = np.linspace(1.999, 1.99999, 200)   # about to cross y = Ly
+    box.v[1, :200] = 5.0
+    _run_parity([box], 3, 1e-3, 10, erpp.F32_FAST)
+    _run_parity([box], 3, 1e-3, 10, erpp.F64_PLAIN)
+
+
+def test_batched_uneven_boxes_and_graph():
+    """Workload-5 shape, reduced: uneven boxes (incl. an empty one) in one
+    launch per stage, replayed through a HIP graph."""
+    _cuda()
+    w = workloads.config(5, nbox=6)
+    boxes = []
+    for i, spec in enumerate(w.boxes):
+        npb = [0, 37, 1500, 4000, 900, 2500][i]
+        n = [(32,) * 3, (32,) * 3, (64,) * 3, (48,) * 3, (40, 32, 36), (32,) * 3][i]
+        spec = workloads.dataclasses.replace(spec, np_=npb, n=n, kmax=8.0,
+                                             L=tuple(2 * math.pi * a / 32 for a in n))
+        boxes.append(workloads.make_box(spec))
+    _run_parity(boxes, w.M, w.dt, w.M + 4, erpp.F32_FAST, graph=True, tile=(16, 16, 8))
+
+
+def test_graph_replay_equals_eager():
+    _cuda()
+    w = workloads.config(1, np_=700)
+    box = workloads.make_boxes(w)[0]
+    outs = []
+    for graph in (False, True):
+        db = upload(box, w.M, erpp.F32_FAST)
+        with erpp.Plan([db], w.M, w.dt) as plan:
+            if graph:
+                plan.run(0, 12, graph=True)
+            else:
+                for n in range(12):
+                    plan.step(n)
+            torch.cuda.synchronize()
+            outs.append((db.x.cpu().numpy(), db.v.cpu().numpy(), db.f.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert rel_l2(outs[1][2], outs[0][2]) < 1e-6
+
+
+def test_repeat_runs_bins_identical_forcing_within_tolerance():
+    _cuda()
+    w = workloads.config(3, np_=30000, n=(64, 32, 32), L=(4 * math.pi / 4, 2 * math.pi / 4,
+                                                          2 * math.pi / 4), n_blobs=50)
+    box = workloads.make_boxes(w)[0]
+    fs, keys = [], []
+    for _ in range(2):
+        db = upload(box, w.M, erpp.F32_FAST)
+        with erpp.Plan([db], w.M, w.dt) as plan:
+            for n in range(w.M + 2):
+                plan.step(n)
+            key, perm, start = plan.bin(0, db.ring_x[(w.M + 1 - w.M) % (w.M + 1)])
+            torch.cuda.synchronize()
+            fs.append(db.f.double().cpu().numpy())
+            keys.append((key.cpu().numpy(), start.cpu().numpy()))
+    assert np.array_equal(keys[0][0], keys[1][0]) and np.array_equal(keys[0][1], keys[1][1])
+    assert rel_l2(fs[0], fs[1]) < 1e-6
+
+
+def test_tuner_picks_a_valid_tile(tmp_path):
+    _cuda()
+    w = workloads.config(2, np_=20000, n=(64, 64, 64))
+    box = workloads.make_boxes(w)[0]
+    db = upload(box, w.M, erpp.F32_FAST)
+    cache = str(tmp_path / "tune.txt")
+    with erpp.Plan([db], w.M, w.dt) as plan:
+        for n in range(w.M + 1):
+            plan.step(n)
+        plan.tune(cache)
+        t = plan.get_tile()
+        assert all(4 <= a <= 64 for a in t)
+    db2 = upload(box, w.M, erpp.F32_FAST)
+    with erpp.Plan([db2], w.M, w.dt) as plan2:
+        plan2.tune(cache)                       # cache hit, no timing
+        assert plan2.get_tile() == t
