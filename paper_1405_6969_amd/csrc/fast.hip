@@ -190,7 +190,7 @@ struct Visit {
     int pid;               // particle index (FP64 fallback of the sphere test)
 };
 
-constexpr int kVisCap = 2048;   // visits staged per round
+constexpr int kVisCap = 640;    // visits staged per round (2 workgroups per CU fit in LDS)
 constexpr int kVisBuckets = 24; // work classes (clipped stencil-box volume, ratio sqrt 2)
 
 __device__ __forceinline__ int work_bucket(int vol) {
@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
     const int e2 = min(B.T[2], B.n[2] - o2);
     const int PX = B.T[0] + 1;
     const int PL = B.T[1] * PX;
-    const int CS = B.T[2] * PL;
+    const int CS = B.T[2] * PL;        // nodes of the padded tile; component c of node a at 3a+c
     Visit *vis = (Visit *)(acc + 3 * CS + ((3 * CS) & 1));   // 8-byte aligned after the tile
     int *vkey = (int *)(vis + kVisCap);                         // bucket << 16 | rank in bucket
     int *vperm = vkey + kVisCap;                                // visits in work order
@@ -342,8 +342,10 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
                 }
                 const int nv0 = s_nvis;
                 __syncthreads();
-                if (nv0 + kScatterBlock > kVisCap) break;
-                const int chunk = min(re - r, kScatterBlock);
+                // a chunk of c records adds at most c visits
+                const int room = kVisCap - nv0;
+                if (room < 64) break;
+                const int chunk = min(min(re - r, kScatterBlock), room);
                 if (tid < chunk) {
                     const int rr = r + tid;
                     const float4 qa = rec[2 * (int64_t)rr];
@@ -419,14 +421,15 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
                         const float t0 = ((float)lo - v.phx) * hx;
                         float w = exp2f(-(t0 * t0) * c) * gyz;
                         float rr = exp2f(-c * hx * fmaf(2.0f, t0, hx));
-                        int a = (mz + dl2) * PL + (my + dl1) * PX + dl0 + lo;
+                        uint32_t *ap =
+                            (uint32_t *)&acc[3 * ((mz + dl2) * PL + (my + dl1) * PX + dl0 + lo)];
                         for (int m = lo; m <= hi; ++m) {
-                            atomicAdd((uint32_t *)&acc[a], fixed32(v.ax * w));
-                            atomicAdd((uint32_t *)&acc[CS + a], fixed32(v.ay * w));
-                            atomicAdd((uint32_t *)&acc[2 * CS + a], fixed32(v.az * w));
+                            atomicAdd(ap, fixed32(v.ax * w));
+                            atomicAdd(ap + 1, fixed32(v.ay * w));
+                            atomicAdd(ap + 2, fixed32(v.az * w));
                             w *= rr;
                             rr *= qx;
-                            ++a;
+                            ap += 3;
                         }
                     }
                 }
@@ -448,10 +451,10 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
         const int ly = (i / e0) % e1;
         const int lz = i / (e0 * e1);
         const int64_t g = ((int64_t)(o2 + lz) * Ny + (o1 + ly)) * Nx + (o0 + lx);
-        const int a = lz * PL + ly * PX + lx;
+        const int a = 3 * (lz * PL + ly * PX + lx);
         f[g] = (float)acc[a] * inv;
-        f[ng + g] = (float)acc[CS + a] * inv;
-        f[2 * ng + g] = (float)acc[2 * CS + a] * inv;
+        f[ng + g] = (float)acc[a + 1] * inv;
+        f[2 * ng + g] = (float)acc[a + 2] * inv;
     }
 }
 
