@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-steps", type=int, default=10)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one plain device copy of MIB MiB (the reference kernel "
+                         "for scaling HBM counter readings)")
     return ap.parse_args()
 
 
@@ -231,6 +234,15 @@ def main():
         log(f"[bench] oracle {cpu}")
 
     plan.close()
+    if args.copy_calibration > 0:
+        nel = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {args.copy_calibration} MiB read + written")
+        del src, dst
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "particle-steps/s", "n_gpus": 1,
         "steps": K, "warmup": W, "ms_per_step": round(ms_step, 6), "higher_is_better": True,
