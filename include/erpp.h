@@ -6,7 +6,7 @@
  * particle method for multi-phase flows in the two-way coupling regime",
  * arXiv:1405.6969.  One coupling step n of every box does, in order:
  *
- *   1. bin      -- sort the particles whose drag is being injected by grid tile
+ *   1. bin      -- sort the particles whose drag is being injected by grid cell
  *                  (locality structure for the scatter; not in the paper);
  *   2. evaluate -- for each particle read the history ring at level n-M
  *                  (position and drag delayed by eps_R = M dt, Sec. 2.3,
@@ -107,10 +107,14 @@ erpp_status erpp_plan_create(erpp_plan **plan, const erpp_box *boxes, int32_t nb
                              int32_t self_correction, void *stream);
 
 /* Scatter tile shape (nodes per tile in x, y, z) of an ERPP_F32_FAST plan.
- * Each entry in [4, 64], tile_x * tile_y * tile_z <= 8192 and the LDS copy of
- * the tile (24 bytes per node, rows padded by one node) <= 150 KiB.  Per box the
- * tile is clipped so that a stencil never wraps onto a tile twice.  Invalidates
- * a captured graph. */
+ * Each entry in [4, 64] and tile_x * tile_y * tile_z <= 8192.  Per box the tile
+ * is clipped so that a stencil never wraps onto a tile twice.  The tile must fit
+ * the scatter's LDS for every box of the plan: an int32 copy of the tile
+ * (12 bytes per node, rows padded by one node), the list of the tile's particle
+ * window (two ints per cell-row segment, at most 1024 cell rows
+ * (tile_y + S_y - 1)(tile_z + S_z - 1), S = stencil width in nodes) and at least
+ * 256 staged particle records of 32 bytes, within 150 KiB; otherwise
+ * ERPP_EINVAL and the plan keeps its tile.  Invalidates a captured graph. */
 erpp_status erpp_plan_set_tile(erpp_plan *plan, const int32_t tile[3]);
 erpp_status erpp_plan_get_tile(const erpp_plan *plan, int32_t tile[3]);
 
@@ -121,15 +125,16 @@ erpp_status erpp_plan_get_tile(const erpp_plan *plan, int32_t tile[3]);
  * `stream`.  On ERPP_F64_PLAIN plans it is a no-op. */
 erpp_status erpp_plan_tune(erpp_plan *plan, const char *cache_path, void *stream);
 
-/* Number of scatter bins (tiles) of box `ibox` for erpp_bin. */
+/* Number of bins of box `ibox` for erpp_bin: its grid cells, Nx * Ny * Nz. */
 erpp_status erpp_plan_bins(const erpp_plan *plan, int32_t ibox, int32_t *nbin);
 
 /* Bin `pos` ([3][np] device FP64 positions of box ibox, e.g. x^n or a ring
- * level) by the plan's tiles: key[p] = (k Ny + j) Nx + i is the cell of the
- * wrapped position (i = min(floor(x/dx), N-1)); perm lists the particles grouped
- * by tile in ascending tile order, bin_start[nbin+1] delimits the groups (order
- * inside a group unspecified).  key, perm, bin_start: device, caller-owned,
- * sizes np, np, nbin+1. */
+ * level) by grid cell (stage 1; the cell rule of Sec. 2.4's lattice, nodes at
+ * i dx): key[p] = (k Ny + j) Nx + i is the cell of the wrapped position
+ * (i = min(floor(x/dx), N-1), per dimension); bin_start[0..ncell] is the
+ * exclusive scan of the cell counts and perm lists the particles grouped by cell
+ * in ascending key order (order inside a cell unspecified).  key, perm,
+ * bin_start: device, caller-owned, sizes np, np, ncell+1. */
 erpp_status erpp_bin(erpp_plan *plan, int32_t ibox, const double *pos, int32_t *key,
                      int32_t *perm, int32_t *bin_start, void *stream);
 

@@ -61,7 +61,7 @@ void free_scratch(erpp_plan *p) {
     (void)hipFree(s.start);
     (void)hipFree(s.rank);
     (void)hipFree(s.rec);
-    (void)hipFree(s.binmax);
+    (void)hipFree(s.part);
     (void)hipFree(s.pamp);
     (void)hipFree(s.pphi);
     (void)hipFree(s.pbase);
@@ -91,21 +91,15 @@ erpp_status upload_boxes(erpp_plan *p) {
     return ERPP_OK;
 }
 
-// (Re)allocate the bin arrays after a tile change.
+// Cell histogram, its scan and the scan partials (sized by the cells of all boxes).
 erpp_status alloc_bins(erpp_plan *p) {
-    (void)hipFree(p->s.count);
-    (void)hipFree(p->s.start);
-    (void)hipFree(p->s.binmax);
-    p->s.count = nullptr;
-    p->s.start = nullptr;
-    p->s.binmax = nullptr;
-    if (alloc(&p->s.count, (size_t)p->nbins_total) != hipSuccess ||
-        alloc(&p->s.start, (size_t)p->nbins_total + 1) != hipSuccess ||
-        alloc(&p->s.binmax, (size_t)p->nbins_total) != hipSuccess)
-        return fail(ERPP_ENOMEM, "bin arrays (%lld bins)", (long long)p->nbins_total);
-    HIP_OR_RETURN(hipMemset(p->s.binmax, 0, sizeof(uint32_t) * (size_t)std::max<int64_t>(p->nbins_total, 1)));
-    HIP_OR_RETURN(hipMemset(p->s.count, 0, sizeof(int32_t) * (size_t)std::max<int64_t>(p->nbins_total, 1)));
-    HIP_OR_RETURN(hipMemset(p->s.start, 0, sizeof(int32_t) * (size_t)(p->nbins_total + 1)));
+    const size_t nc = (size_t)std::max<int64_t>(p->ncell_total, 1);
+    const size_t nchunk = (nc + erpp::kScanChunk - 1) / erpp::kScanChunk;
+    if (alloc(&p->s.count, nc) != hipSuccess || alloc(&p->s.start, nc + 1) != hipSuccess ||
+        alloc(&p->s.part, nchunk + 1) != hipSuccess)
+        return fail(ERPP_ENOMEM, "cell arrays (%lld cells)", (long long)p->ncell_total);
+    HIP_OR_RETURN(hipMemset(p->s.count, 0, sizeof(int32_t) * nc));
+    HIP_OR_RETURN(hipMemset(p->s.start, 0, sizeof(int32_t) * (nc + 1)));
     return ERPP_OK;
 }
 
@@ -117,9 +111,6 @@ erpp_status check_tile(const int32_t tile[3]) {
     if ((int64_t)tile[0] * tile[1] * tile[2] > erpp::kMaxTileVol)
         return fail(ERPP_EINVAL, "tile volume %lld > %d",
                     (long long)tile[0] * tile[1] * tile[2], erpp::kMaxTileVol);
-    if (erpp::scatter_lds_bytes(tile) > erpp::kMaxScatterLds)
-        return fail(ERPP_EINVAL, "tile needs %zu bytes of LDS (> %zu)", erpp::scatter_lds_bytes(tile),
-                    erpp::kMaxScatterLds);
     return ERPP_OK;
 }
 
@@ -152,18 +143,25 @@ hipError_t advance_step(erpp_plan *p, hipStream_t st) {
     return hipGetLastError();
 }
 
-void fill_box_tiles(erpp_plan *p) {
-    int64_t bin = 0, bp = 0, bt = 0, br = 0;
+static int32_t round4(int64_t v) { return (int32_t)((v + 3) & ~int64_t(3)); }
+
+// Tiles, block offsets and the scatter's LDS layout of every box for the plan's
+// tile.  Returns false when the tile does not fit (window rows or LDS).
+bool fill_box_tiles(erpp_plan *p) {
+    int64_t cell = 0, bp = 0, bt = 0, br = 0;
+    int64_t fixed_max = 0;
+    bool ok = true;
     for (auto &B : p->hbox) {
+        int32_t ext[3];
         for (int d = 0; d < 3; ++d) {
-            int32_t ext = B.mhi[d] - B.mlo[d] + 1;
-            int32_t T = std::min(p->tile[d], B.n[d] - ext);
+            ext[d] = B.mhi[d] - B.mlo[d] + 1;
+            int32_t T = std::min(p->tile[d], B.n[d] - ext[d]);
             if (T < 1) T = 1;
             B.T[d] = T;
             B.ntile[d] = (B.n[d] + T - 1) / T;
         }
-        B.bin_off = bin;
-        bin += (int64_t)B.ntile[0] * B.ntile[1] * B.ntile[2];
+        B.cell_off = cell;
+        cell += (int64_t)B.n[0] * B.n[1] * B.n[2];
         B.blk_p = bp;
         bp += (B.np + kBlock - 1) / kBlock;
         B.blk_t = bt;
@@ -171,12 +169,27 @@ void fill_box_tiles(erpp_plan *p) {
         B.rows = (int64_t)(B.mhi[1] - B.mlo[1] + 1) * (B.mhi[2] - B.mlo[2] + 1);
         B.blk_r = br;
         br += (B.np * B.rows + kBlock - 1) / kBlock;
+        // scatter LDS: int32 tile [3][T2][T1][T0+1], window offsets [2 rows + 1],
+        // segment starts [2 rows], staged records (2 float4 each)
+        const int64_t wrows = (int64_t)(B.T[1] + ext[1] - 1) * (B.T[2] + ext[2] - 1);
+        if (wrows > kMaxWinRows) ok = false;
+        B.wrows = (int32_t)std::min<int64_t>(wrows, kMaxWinRows);
+        const int64_t accw = 3 * (int64_t)B.T[2] * B.T[1] * (B.T[0] + 1);
+        B.lds_woff = round4(accw);
+        B.lds_wseg = B.lds_woff + round4(2 * wrows + 1);
+        B.lds_stage = (B.lds_wseg + round4(2 * wrows)) / 4;
+        fixed_max = std::max<int64_t>(fixed_max, 16 * (int64_t)B.lds_stage);
     }
-    p->nbins_total = bin;
+    int64_t cap = ((int64_t)kScatterLdsTarget - fixed_max) / 32;
+    cap = std::max<int64_t>(kMinStage, std::min<int64_t>(kMaxStage, cap));
+    for (auto &B : p->hbox) B.stage_cap = (int32_t)cap;
+    p->ncell_total = cell;
     p->pblocks = bp;
     p->tblocks = bt;
     p->pblocks_rows = br;
-    p->lds_bytes = scatter_lds_bytes(p->tile);
+    p->lds_bytes = (size_t)(fixed_max + 32 * cap);
+    if (p->lds_bytes > kMaxScatterLds) ok = false;
+    return ok;
 }
 
 }  // namespace erpp
@@ -288,7 +301,14 @@ erpp_status erpp_plan_create(erpp_plan **out, const erpp_box *boxes, int32_t nbo
     p->boxes.assign(boxes, boxes + nbox);
     p->hbox = hb;
     p->np_total = np_total;
-    erpp::fill_box_tiles(p);
+    if (!erpp::fill_box_tiles(p)) {
+        // the default tile is too large for these stencils: fall back to the smallest
+        for (int d = 0; d < 3; ++d) p->tile[d] = 4;
+        if (!erpp::fill_box_tiles(p)) {
+            delete p;
+            return fail(ERPP_EUNSUPPORTED, "stencil too wide for the scatter's LDS tile");
+        }
+    }
     bool ok = alloc(&p->dbox, (size_t)nbox) == hipSuccess && alloc(&p->s.step, 1) == hipSuccess &&
               alloc(&p->s.rank, (size_t)np_total) == hipSuccess;
     if (ok && prec == ERPP_F32_FAST) ok = alloc(&p->s.rec, 2 * (size_t)np_total) == hipSuccess;
@@ -319,14 +339,19 @@ erpp_status erpp_plan_set_tile(erpp_plan *p, const int32_t tile[3]) {
     if (!p) return fail(ERPP_EINVAL, "plan is NULL");
     erpp_status s = check_tile(tile);
     if (s != ERPP_OK) return s;
-    for (int d = 0; d < 3; ++d) p->tile[d] = tile[d];
-    int64_t old = p->nbins_total;
-    erpp::fill_box_tiles(p);
-    drop_graph(p);
-    if (p->nbins_total != old) {
-        s = alloc_bins(p);
-        if (s != ERPP_OK) return s;
+    int32_t old[3];
+    for (int d = 0; d < 3; ++d) {
+        old[d] = p->tile[d];
+        p->tile[d] = tile[d];
     }
+    if (!erpp::fill_box_tiles(p)) {
+        const size_t need = p->lds_bytes;
+        for (int d = 0; d < 3; ++d) p->tile[d] = old[d];
+        erpp::fill_box_tiles(p);
+        return fail(ERPP_EINVAL, "tile %dx%dx%d does not fit the scatter's LDS (%zu bytes, "
+                    "window rows <= %d)", tile[0], tile[1], tile[2], need, erpp::kMaxWinRows);
+    }
+    drop_graph(p);
     return upload_boxes(p);
 }
 
@@ -340,7 +365,7 @@ erpp_status erpp_plan_bins(const erpp_plan *p, int32_t ibox, int32_t *nbin) {
     if (!p || !nbin) return fail(ERPP_EINVAL, "NULL argument");
     if (ibox < 0 || ibox >= p->nbox) return fail(ERPP_EINVAL, "ibox %d out of range", ibox);
     const erpp::DevBox &B = p->hbox[ibox];
-    *nbin = B.ntile[0] * B.ntile[1] * B.ntile[2];
+    *nbin = B.n[0] * B.n[1] * B.n[2];
     return ERPP_OK;
 }
 
@@ -435,7 +460,7 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
     hipStream_t st = as_stream(stream);
     // geometry key
     std::ostringstream key;
-    key << "v1 M" << p->M << " nbox" << p->nbox;
+    key << "v2 M" << p->M << " nbox" << p->nbox;
     for (const auto &B : p->hbox)
         key << " " << B.n[0] << "x" << B.n[1] << "x" << B.n[2] << ":" << B.np << ":" << B.mlo[0]
             << "," << B.mhi[0];
@@ -452,9 +477,9 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
                 return erpp_plan_set_tile(p, t);
         }
     }
-    static const int32_t cand[][3] = {{8, 8, 8},   {16, 8, 8},   {16, 16, 8}, {16, 16, 16},
-                                      {32, 8, 8},  {32, 16, 8},  {32, 16, 16}, {32, 32, 8},
-                                      {64, 8, 8},  {64, 16, 8},  {16, 16, 32}, {32, 8, 16}};
+    static const int32_t cand[][3] = {{64, 8, 8},  {32, 8, 8},   {64, 8, 4},  {64, 4, 8},
+                                      {32, 16, 8}, {32, 8, 16},  {16, 16, 16}, {16, 8, 8},
+                                      {32, 4, 8},  {64, 16, 4},  {32, 16, 16}, {16, 16, 8}};
     const int ncand = (int)(sizeof cand / sizeof cand[0]);
     int32_t best[3] = {p->tile[0], p->tile[1], p->tile[2]};
     float best_ms = 1e30f;
@@ -468,8 +493,7 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
     erpp_status status = ERPP_OK;
     for (int c = 0; c < ncand && status == ERPP_OK; ++c) {
         if (check_tile(cand[c]) != ERPP_OK) continue;
-        status = erpp_plan_set_tile(p, cand[c]);
-        if (status != ERPP_OK) break;
+        if (erpp_plan_set_tile(p, cand[c]) != ERPP_OK) continue;   // does not fit these boxes
         status = erpp_scatter(p, n, stream);   // warm-up
         if (status != ERPP_OK) break;
         (void)hipEventRecord(a, st);

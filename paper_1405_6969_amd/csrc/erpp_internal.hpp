@@ -15,6 +15,11 @@ constexpr int kMaxTileDim = 64;
 constexpr int kMaxTileVol = 8192;
 constexpr int kBlock = 256;          // threads per block of particle kernels
 constexpr int kScatterBlock = 512;   // threads per block of the tiled scatter
+constexpr int kScatterWaves = kScatterBlock / 64;
+constexpr int kScanChunk = 4096;     // counters per block of the device-wide scan
+constexpr int kMaxWinRows = 1024;    // cell rows of a scatter tile's particle window
+constexpr int kMinStage = 256;       // smallest staging buffer (records) of a scatter round
+constexpr int kMaxStage = 4096;
 
 // Everything a kernel needs to know about one box; lives in device memory as
 // an array indexed by box.  Plain old data.
@@ -24,10 +29,14 @@ struct DevBox {
     int32_t mhi[3];
     int32_t T[3];        // scatter tile (nodes) of this box, clipped
     int32_t ntile[3];    // tiles per dimension
-    int32_t pad0;
+    int32_t wrows;       // cell rows (y, z) of a tile's particle window
+    int32_t lds_woff;    // LDS word offsets: window offsets, segment starts, staged records
+    int32_t lds_wseg;
+    int32_t lds_stage;   // (in 16-byte units)
+    int32_t stage_cap;   // records staged per round
     int64_t np;          // particles
     int64_t poff;        // first particle in the concatenated particle space
-    int64_t bin_off;     // first bin (tile) of this box in the global bin array
+    int64_t cell_off;    // first cell of this box in the concatenated cell-key space
     int64_t blk_p;       // first block of this box in particle launches
     int64_t blk_t;       // first block of this box in tile launches
     int64_t blk_r;       // first block of this box in (particle, row) launches
@@ -56,11 +65,11 @@ struct DevBox {
 
 struct Scratch {
     // ERPP_F32_FAST
-    int32_t *count = nullptr;    // [nbins_total]   per-step histogram (kept zero at rest)
-    int32_t *start = nullptr;    // [nbins_total+1] exclusive scan
-    int32_t *rank = nullptr;     // [np_total]      rank of a particle inside its bin
-    float4 *rec = nullptr;       // [2*np_total]    tile-sorted injection records
-    uint32_t *binmax = nullptr;  // [nbins_total]   largest |amplitude| per bin (float bits)
+    int32_t *count = nullptr;    // [ncell_total]   per-step cell histogram (kept zero at rest)
+    int32_t *start = nullptr;    // [ncell_total+1] exclusive scan of count
+    int32_t *part = nullptr;     // [nchunk+1]      scan partials
+    int32_t *rank = nullptr;     // [np_total]      rank of a particle inside its cell
+    float4 *rec = nullptr;       // [2*np_total]    cell-sorted injection records
     // ERPP_F64_PLAIN
     double *pamp = nullptr;      // [4][np_total] -D/rho_f (3 components) and Z
     double *pphi = nullptr;      // [3][np_total] offsets inside the base cell
@@ -83,7 +92,7 @@ struct erpp_plan {
     std::vector<erpp::DevBox> hbox;
     erpp::DevBox *dbox = nullptr;
     int64_t np_total = 0;
-    int64_t nbins_total = 0;
+    int64_t ncell_total = 0;
     int64_t pblocks = 0;         // blocks of particle launches (box aligned)
     int64_t tblocks = 0;         // blocks of tile launches
     int64_t pblocks_rows = 0;    // plain scatter: blocks over (particle,row)
@@ -107,8 +116,10 @@ hipError_t plain_scatter_stages(erpp_plan *p, hipStream_t st);
 hipError_t plain_update_stage(erpp_plan *p, hipStream_t st);
 hipError_t set_step(erpp_plan *p, int64_t n, hipStream_t st);
 hipError_t advance_step(erpp_plan *p, hipStream_t st);
-void fill_box_tiles(erpp_plan *p);          // recompute tiles/bins/blocks on host
-size_t scatter_lds_bytes(const int32_t tile[3]);   // int32 tile + staged visits
+bool fill_box_tiles(erpp_plan *p);          // tiles, blocks, LDS layout; false if it does not fit
+hipError_t scan_counts(int32_t *count, int64_t n, int32_t *start, int32_t *part,
+                       hipStream_t st);     // start = exclusive scan of count; count = 0
 hipError_t fast_prepare_lds(size_t bytes);         // opt the scatter into > 64 KB LDS
 constexpr size_t kMaxScatterLds = 150 * 1024;
+constexpr size_t kScatterLdsTarget = 74 * 1024;   // two workgroups per CU (with static LDS)
 }  // namespace erpp

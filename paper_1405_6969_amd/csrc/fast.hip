@@ -1,15 +1,16 @@
 // fast.hip -- ERPP_F32_FAST path of the coupling step for gfx950.
 //
 // Per step n (all boxes of a plan in one launch per stage):
-//   k_bin_count   tile histogram of the delayed positions X^{n-M}; a particle's
-//                 atomic ticket is its rank inside its tile
-//   k_scan        exclusive scan of the histogram (and reset of it)
+//   k_bin_count   cell histogram of the delayed positions X^{n-M}; a particle's
+//                 atomic ticket is its rank inside its cell
+//   k_scan_*      device-wide exclusive scan of the histogram (and its reset)
 //   k_eval        per particle: FP64 cell/offset of X^{n-M}, FP32 Gaussian
 //                 normalisation over the 3-sigma sphere, record
-//                 {offsets, amplitude} written at its tile-sorted slot
-//   k_scatter     one workgroup per tile: accumulate the stencils of every
-//                 particle that reaches the tile into an LDS tile, then store
-//                 the tile (each node written once, no global atomics)
+//                 {offsets, amplitude} written at its cell-sorted slot
+//   k_scatter     one workgroup per tile of nodes: the stencil rows of every
+//                 particle that reaches the tile are accumulated into an LDS
+//                 copy of the tile, which is then stored (each node written
+//                 once, no global atomics)
 //   k_update      per particle: trilinear carrier, closed-form self term,
 //                 Stokes drag, history write, explicit Euler, wrap
 #include <hip/hip_runtime.h>
@@ -21,8 +22,8 @@ namespace erpp {
 
 namespace {
 
-__device__ __forceinline__ int tile_of(const DevBox &B, int b0, int b1, int b2) {
-    return ((b2 / B.T[2]) * B.ntile[1] + (b1 / B.T[1])) * B.ntile[0] + (b0 / B.T[0]);
+__device__ __forceinline__ int64_t cell_key(const DevBox &B, int b0, int b1, int b2) {
+    return ((int64_t)b2 * B.n[1] + b1) * B.n[0] + b0;
 }
 
 __global__ void __launch_bounds__(kBlock) k_bin_count(const DevBox *__restrict__ Bs, int nbox,
@@ -41,50 +42,119 @@ __global__ void __launch_bounds__(kBlock) k_bin_count(const DevBox *__restrict__
     int b[3];
     double ph;
     for (int d = 0; d < 3; ++d) cell_of(X[d * np + p], B.L[d], B.dx[d], B.n[d], b[d], ph);
-    const int t = tile_of(B, b[0], b[1], b[2]);
-    rank[B.poff + p] = atomicAdd(&count[B.bin_off + t], 1);
+    rank[B.poff + p] = atomicAdd(&count[B.cell_off + cell_key(B, b[0], b[1], b[2])], 1);
 }
 
-// Exclusive scan of count[0..nb) into start[0..nb], count (and the per-bin
-// amplitude bound, when given) reset to zero.  One workgroup of 1024 threads,
-// each owning a contiguous chunk.
-__global__ void __launch_bounds__(1024) k_scan(int32_t *__restrict__ count,
-                                               int32_t *__restrict__ start, int64_t nb,
-                                               uint32_t *__restrict__ binmax) {
-    __shared__ int32_t part[1024];
-    const int tid = threadIdx.x;
-    const int64_t chunk = (nb + 1023) / 1024;
-    const int64_t a = tid * chunk;
-    const int64_t e = (a + chunk < nb) ? a + chunk : nb;
-    int32_t s = 0;
-    for (int64_t i = a; i < e; ++i) s += count[i];
-    part[tid] = s;
+// ------------------------------------------------------------------ scan ----
+// start[0..n] = exclusive scan of count[0..n), count reset to zero.  Three
+// launches: per-chunk sums, scan of the chunk sums (one workgroup), per-chunk
+// scan with its offset.  Chunks of kScanChunk counters, 256 threads x 16.
+
+__device__ __forceinline__ int wave_incl_scan(int x) {
+    const int lane = threadIdx.x & 63;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan of one value per thread over the workgroup (nw waves); *total
+// receives the sum.  sw: nw ints of LDS.  Contains barriers: call uniformly.
+__device__ __forceinline__ int block_excl_scan(int v, int *sw, int nw, int *total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int x = wave_incl_scan(v);
+    if (lane == 63) sw[w] = x;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int32_t v = (tid >= off) ? part[tid - off] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
+    int pre = 0, tot = 0;
+    for (int k = 0; k < nw; ++k) {
+        const int t = sw[k];
+        pre += (k < w) ? t : 0;
+        tot += t;
     }
-    int32_t run = part[tid] - s;
-    for (int64_t i = a; i < e; ++i) {
-        int32_t c = count[i];
-        start[i] = run;
-        run += c;
-        count[i] = 0;
-        if (binmax) binmax[i] = 0u;
-    }
-    if (tid == 1023) start[nb] = part[1023];
+    __syncthreads();
+    *total = tot;
+    return pre + x - v;
 }
 
+__global__ void __launch_bounds__(256) k_scan_reduce(const int32_t *__restrict__ count,
+                                                     int64_t n, int32_t *__restrict__ part) {
+    __shared__ int sw[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    int s = 0;
+    for (int j = 0; j < kScanChunk / 256; ++j) {
+        const int64_t i = base + j * 256 + threadIdx.x;
+        if (i < n) s += count[i];
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = sw[0] + sw[1] + sw[2] + sw[3];
+}
+
+// part[0..nchunk) -> exclusive scan in place, part[nchunk] = total.
+__global__ void __launch_bounds__(1024) k_scan_top(int32_t *__restrict__ part, int64_t nchunk) {
+    __shared__ int sw[16];
+    const int64_t per = (nchunk + 1023) / 1024;
+    const int64_t a = threadIdx.x * per;
+    const int64_t e = (a + per < nchunk) ? a + per : nchunk;
+    int s = 0;
+    for (int64_t i = a; i < e; ++i) s += part[i];
+    int total;
+    int run = block_excl_scan(s, sw, 16, &total);
+    for (int64_t i = a; i < e; ++i) {
+        const int c = part[i];
+        part[i] = run;
+        run += c;
+    }
+    if (threadIdx.x == 0) part[nchunk] = total;
+}
+
+__global__ void __launch_bounds__(256) k_scan_down(int32_t *__restrict__ count, int64_t n,
+                                                   const int32_t *__restrict__ part,
+                                                   int64_t nchunk, int32_t *__restrict__ start) {
+    // chunk staged in LDS with one pad word per 16 (thread t owns 16 consecutive)
+    __shared__ int buf[kScanChunk + kScanChunk / 16];
+    __shared__ int sw[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    const int t = threadIdx.x;
+    for (int j = 0; j < kScanChunk / 256; ++j) {
+        const int k = j * 256 + t;
+        const int64_t i = base + k;
+        int c = 0;
+        if (i < n) {
+            c = count[i];
+            count[i] = 0;
+        }
+        buf[k + (k >> 4)] = c;
+    }
+    __syncthreads();
+    int s = 0;
+    for (int j = 0; j < 16; ++j) s += buf[t * 17 + j];
+    int total;
+    int run = block_excl_scan(s, sw, 4, &total) + part[blockIdx.x];
+    for (int j = 0; j < 16; ++j) {
+        const int c = buf[t * 17 + j];
+        buf[t * 17 + j] = run;
+        run += c;
+    }
+    __syncthreads();
+    for (int j = 0; j < kScanChunk / 256; ++j) {
+        const int k = j * 256 + t;
+        const int64_t i = base + k;
+        if (i < n) start[i] = buf[k + (k >> 4)];
+    }
+    if (blockIdx.x == 0 && t == 0) start[n] = part[nchunk];
+}
+
+// ------------------------------------------------------------------ eval ----
 constexpr int kMaxOff = 16;   // max stencil offsets per dimension (mhi - mlo + 1)
 
 __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, int nbox,
                                                  const int64_t *__restrict__ stepp, int M,
                                                  const int32_t *__restrict__ start,
                                                  const int32_t *__restrict__ rank,
-                                                 float4 *__restrict__ rec,
-                                                 uint32_t *__restrict__ binmax) {
+                                                 float4 *__restrict__ rec) {
     __shared__ float sP[kMaxOff + 1][kBlock];   // prefix sums of the x factors
     __shared__ float sGy[kMaxOff][kBlock];
     __shared__ float sTy[kMaxOff][kBlock];
@@ -141,106 +211,68 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
     const float Zv = Z * (float)B.dV;
     const float inv = -B.rhof_inv / Zv;
     const float ax = Dd[p] * inv, ay = Dd[np + p] * inv, az = Dd[2 * np + p] * inv;
-    const int t = tile_of(B, b[0], b[1], b[2]);
-    const int64_t slotr = (int64_t)start[B.bin_off + t] + rank[B.poff + p];
+    const int64_t slotr =
+        (int64_t)start[B.cell_off + cell_key(B, b[0], b[1], b[2])] + rank[B.poff + p];
     const uint32_t ijk = (uint32_t)b[0] | ((uint32_t)b[1] << 11) | ((uint32_t)b[2] << 22);
     rec[2 * slotr] = make_float4(phx, phy, phz, __uint_as_float(ijk));
     rec[2 * slotr + 1] = make_float4(ax, ay, az, __int_as_float((int)p));
-    // per-bin bound of the largest amplitude (non-negative floats order as uints)
-    const float amax = fmaxf(fabsf(ax), fmaxf(fabsf(ay), fabsf(az)));
-    atomicMax(&binmax[B.bin_off + t], __float_as_uint(amax));
 }
 
-constexpr int kMaxTileList = 24;
-
-// |v| <= 2^30 by construction of the scale: round to int32, sign-extend to the
-// 64-bit two's-complement word added into the LDS accumulator.
-__device__ __forceinline__ unsigned long long to_fixed(float v) {
-    return (unsigned long long)(long long)__float2int_rn(v);
-}
-
-// Tiles of one dimension holding base cells in [a, c] (unwrapped, c - a < N),
-// written to list[0..*cnt) without duplicates.
-__device__ void tiles_for_range(int a, int c, int N, int T, int *list, int *cnt) {
-    int n = 0;
-    auto add_interval = [&](int u, int v) {
-        for (int t = u / T; t <= v / T; ++t) {
-            bool dup = false;
-            for (int q = 0; q < n; ++q) dup |= (list[q] == t);
-            if (!dup && n < kMaxTileList) list[n++] = t;
-        }
-    };
-    int aw = a % N;
-    if (aw < 0) aw += N;
-    const int len = c - a;
-    if (aw + len < N) {
-        add_interval(aw, aw + len);
-    } else {
-        add_interval(aw, N - 1);
-        add_interval(0, aw + len - N);
-    }
-    *cnt = n;
-}
-
-// A particle whose stencil reaches the tile, as staged in LDS.
-struct Visit {
-    float phx, phy, phz;   // FP32 offsets of the delayed position in its cell
-    float ax, ay, az;      // amplitude / Z, already multiplied by the tile scale
-    int dl;                // base cell relative to the tile origin, 3 x 10 bits (+512)
-    int pid;               // particle index (FP64 fallback of the sphere test)
-};
-
-constexpr int kVisCap = 640;    // visits staged per round (2 workgroups per CU fit in LDS)
-constexpr int kVisBuckets = 24; // work classes (clipped stencil-box volume, ratio sqrt 2)
-
-__device__ __forceinline__ int work_bucket(int vol) {
-    // floor(2 log2(vol)) from the exponent and the top mantissa bit
-    const float fv = (float)vol;
-    const uint32_t u = __float_as_uint(fv);
-    const int e = (int)((u >> 23) & 255u) - 127;
-    const int half = (u >> 22) & 1u;    // mantissa >= 1.5 ~ sqrt(2)
-    const int b = 2 * e + half;
-    return b < 0 ? 0 : (b >= kVisBuckets ? kVisBuckets - 1 : b);
+// --------------------------------------------------------------- scatter ----
+__device__ __forceinline__ int wrap_index(int i, int N) {
+    i %= N;
+    return i < 0 ? i + N : i;
 }
 
 // Contribution to the integer tile: round to the nearest int32 (|v| < 2^30 by
 // the choice of scale; the error of one term is at most half a unit).
 __device__ __forceinline__ uint32_t fixed32(float v) { return (uint32_t)__float2int_rn(v); }
 
-__device__ __forceinline__ int pack_dl(int a, int b, int c) {
-    return (a + 512) | ((b + 512) << 10) | ((c + 512) << 20);
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // One workgroup per tile of nodes (owner computes: every node of the tile is
-// written once, by this workgroup; no global atomics).  Every particle whose
-// stencil reaches the tile -- found in the bins of the tile and its neighbours --
-// is a "visit": it adds the part of its stencil inside the tile to an LDS copy
-// of the tile.
+// written once, by this workgroup; no global atomics).
+//
+// Window.  The particles whose stencil can reach the tile have their base cell
+// in the tile grown by the stencil extent.  Records are sorted by cell, so the
+// window is one contiguous record range per (cell row y, z, x-part) -- a
+// "segment"; at most two x-parts when the window wraps in x.  The segments are
+// listed in window order (z, y, x-part); the window offset of a record is its
+// position in that concatenation.
+//
+// Row classes.  Every stencil row of a particle is a relative offset (dy, dz)
+// from its base cell -- its class.  For class (dy, dz) the particles whose row
+// lies on tile plane z and inside the tile in y are those of e1 consecutive
+// window cell rows at fixed window z: one contiguous range of window offsets.
+// A wave takes a class and runs one lane per (particle, row) over the ranges of
+// all tile planes, so its 64 lanes walk rows of the same relative offset, whose
+// x extents differ by at most a node or two -- the inner node loop stays
+// converged.  Records are staged in LDS in rounds of window offsets.
 //
 // Accumulation is exact integer arithmetic: each contribution a*w is rounded to
-// an int32 with the per-tile scale 2^30 / A, where A = sum over the tile's
-// visits of max_c |amplitude| bounds |f| at every node of the tile, and added
-// with ds_add_u32 (the FP32 LDS atomic runs ~40x slower on gfx950).  Integer
-// additions commute, so the forcing does not depend on the order of the adds.
-//
-// Work split: one lane per visit.  A lane walks its clipped stencil plane by
-// plane (z), over the y-range of each plane's disk, and along each row (x) over
-// the exact in-sphere range; along a row the Gaussian weight advances by a
-// multiplicative recurrence (two multiplies per node).
+// an int32 with the per-tile scale 2^30 / A, where A = sum over the window of
+// max_c |amplitude| bounds |f| at every node of the tile (the raw Gaussian is
+// <= 1), and added with ds_add_u32 (the FP32 LDS atomic runs ~40x slower on
+// gfx950).  Integer additions commute, so the forcing does not depend on the
+// order of the adds.
 __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restrict__ Bs,
                                                            int nbox,
                                                            const int64_t *__restrict__ stepp,
                                                            int M,
                                                            const int32_t *__restrict__ start,
                                                            const float4 *__restrict__ rec) {
-    extern __shared__ int32_t acc[];
-    __shared__ int s_list[3][kMaxTileList];
-    __shared__ int s_cnt[3];
-    __shared__ float s_part[kScatterBlock / 64];
+    extern __shared__ int32_t lds[];
+    __shared__ int s_sw[kScatterWaves];
+    __shared__ int s_pre[kScatterWaves][65];
+    __shared__ int s_sa[kScatterWaves][64];
+    __shared__ int s_cls[256];
+    __shared__ int s_ncls;
+    __shared__ float s_part[kScatterWaves];
     __shared__ float s_scale;
-    __shared__ int s_nvis;
-    __shared__ int s_bcnt[kVisBuckets];
-    __shared__ int s_boff[kVisBuckets];
     const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_t; });
     const DevBox &B = Bs[bi];
     const int t = (int)(blockIdx.x - B.blk_t);
@@ -254,190 +286,202 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
     const int PX = B.T[0] + 1;
     const int PL = B.T[1] * PX;
     const int CS = B.T[2] * PL;        // nodes of the padded tile; component c of node a at 3a+c
-    Visit *vis = (Visit *)(acc + 3 * CS + ((3 * CS) & 1));   // 8-byte aligned after the tile
-    int *vkey = (int *)(vis + kVisCap);                         // bucket << 16 | rank in bucket
-    int *vperm = vkey + kVisCap;                                // visits in work order
-    const int tid = threadIdx.x;
+    int32_t *acc = lds;
+    int *woff = lds + B.lds_woff;       // [nseg + 1] window offset of each segment
+    int *wseg = lds + B.lds_wseg;       // [nseg]     first record of each segment
+    float4 *stage = (float4 *)lds + B.lds_stage;   // [2 * stage_cap]
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int i = tid; i < 3 * CS; i += kScatterBlock) acc[i] = 0;
     const int64_t n = *stepp;
-    const bool live = n >= M;
-    // base cells whose stencil reaches the tile, per dimension
-    const int lo0 = o0 - B.mhi[0], hi0 = o0 + e0 - 1 - B.mlo[0];
-    const int lo1 = o1 - B.mhi[1], hi1 = o1 + e1 - 1 - B.mlo[1];
-    const int lo2 = o2 - B.mhi[2], hi2 = o2 + e2 - 1 - B.mlo[2];
-    if (tid < kVisBuckets) s_bcnt[tid] = 0;
-    if (tid == 0) {
-        tiles_for_range(lo0, hi0, B.n[0], B.T[0], s_list[0], &s_cnt[0]);
-        tiles_for_range(lo1, hi1, B.n[1], B.T[1], s_list[1], &s_cnt[1]);
-        tiles_for_range(lo2, hi2, B.n[2], B.T[2], s_list[2], &s_cnt[2]);
-        s_nvis = 0;
-    }
-    __syncthreads();
-    const int nlx = s_cnt[0], nly = s_cnt[1], nlz = s_cnt[2];
-    const int ncb = live ? nlx * nly * nlz : 0;
-    // unwrapped base of record r relative to the tile range; false if it misses
-    auto locate = [&](const float4 &qa, int &d0, int &d1, int &d2) -> bool {
-        const uint32_t ijk = __float_as_uint(qa.w);
-        int bu0 = (int)(ijk & 2047u), bu1 = (int)((ijk >> 11) & 2047u), bu2 = (int)(ijk >> 22);
-        if (bu0 > hi0) bu0 -= B.n[0];
-        if (bu0 < lo0) bu0 += B.n[0];
-        if (bu1 > hi1) bu1 -= B.n[1];
-        if (bu1 < lo1) bu1 += B.n[1];
-        if (bu2 > hi2) bu2 -= B.n[2];
-        if (bu2 < lo2) bu2 += B.n[2];
-        d0 = bu0 - o0;
-        d1 = bu1 - o1;
-        d2 = bu2 - o2;
-        return bu0 >= lo0 && bu0 <= hi0 && bu1 >= lo1 && bu1 <= hi1 && bu2 >= lo2 && bu2 <= hi2;
-    };
-    auto bin_of = [&](int k) -> int64_t {
-        const int ix = k % nlx, iy = (k / nlx) % nly, iz = k / (nlx * nly);
-        return B.bin_off + ((int64_t)s_list[2][iz] * B.ntile[1] + s_list[1][iy]) * B.ntile[0] +
-               s_list[0][ix];
-    };
-    // ---- pass A: amplitude bound of the tile (fixed-order reduction)
-    float part = 0.0f;
-    for (int k = 0; k < ncb; ++k) {
-        const int64_t gb = bin_of(k);
-        const int rs = start[gb], re = start[gb + 1];
-        for (int r = rs + tid; r < re; r += kScatterBlock) {
-            const float4 qa = rec[2 * (int64_t)r];
-            int d0, d1, d2;
-            if (locate(qa, d0, d1, d2)) {
-                const float4 qb = rec[2 * (int64_t)r + 1];
+    const int mlo0 = B.mlo[0], mhi0 = B.mhi[0];
+    const int mlo1 = B.mlo[1], mhi1 = B.mhi[1];
+    const int mlo2 = B.mlo[2], mhi2 = B.mhi[2];
+    float scale = 1.0f;
+    if (n >= M) {
+        const int Nx = B.n[0], Ny = B.n[1], Nz = B.n[2];
+        const int WY = e1 + mhi1 - mlo1;
+        const int WZ = e2 + mhi2 - mlo2;
+        const int nseg = 2 * WY * WZ;
+        const int xa = o0 - mhi0;                 // first base cell in x (unwrapped)
+        const int wx = e0 + mhi0 - mlo0;          // base cells in x (< Nx)
+        const float cut = B.R2f + B.guard;
+        // row classes that some particle can reach: nearest approach of the row to
+        // a base-cell offset in [0, 1)^2 within the cut-off
+        const int ny = mhi1 - mlo1 + 1, nz = mhi2 - mlo2 + 1;
+        if (tid == 0) s_ncls = 0;
+        __syncthreads();
+        if (tid < ny * nz) {
+            const int dy = mlo1 + tid % ny, dz = mlo2 + tid / ny;
+            const float ay = (float)(dy >= 1 ? dy - 1 : -dy) * B.dxf[1];
+            const float az = (float)(dz >= 1 ? dz - 1 : -dz) * B.dxf[2];
+            if (fmaf(ay, ay, az * az) <= cut) s_cls[atomicAdd(&s_ncls, 1)] = tid;
+        }
+        // segment table: counts, then window offsets by a block scan
+        const int per = (nseg + kScatterBlock - 1) / kScatterBlock;
+        const int k0 = tid * per, k1 = min(k0 + per, nseg);
+        int mine = 0;
+        for (int k = k0; k < k1; ++k) {
+            const int r = k >> 1, j = k & 1;
+            const int wy = r % WY, wz = r / WY;
+            const int b1 = wrap_index(o1 - mhi1 + wy, Ny);
+            const int b2 = wrap_index(o2 - mhi2 + wz, Nz);
+            int lo, hi;
+            if (xa < 0) {
+                lo = j ? 0 : xa + Nx;
+                hi = j ? xa + wx - 1 : Nx - 1;
+            } else if (xa + wx > Nx) {
+                lo = j ? 0 : xa;
+                hi = j ? xa + wx - 1 - Nx : Nx - 1;
+            } else {
+                lo = j ? 0 : xa;
+                hi = j ? -1 : xa + wx - 1;
+            }
+            int gs = 0, c = 0;
+            if (lo <= hi) {
+                const int64_t base = B.cell_off + ((int64_t)b2 * Ny + b1) * Nx;
+                gs = start[base + lo];
+                c = start[base + hi + 1] - gs;
+            }
+            wseg[k] = gs;
+            woff[k] = c;
+            mine += c;
+        }
+        int wtot;
+        int run = block_excl_scan(mine, s_sw, kScatterWaves, &wtot);
+        for (int k = k0; k < k1; ++k) {
+            const int c = woff[k];
+            woff[k] = run;
+            run += c;
+        }
+        if (tid == 0) woff[nseg] = wtot;
+        __syncthreads();
+        const int ncls = s_ncls;
+        // window offset -> (segment, record); woff[s] <= q < woff[s + 1]
+        auto record_of = [&](int q, int &sg) -> int {
+            int lo = 0, hi = nseg;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (woff[mid] <= q) lo = mid; else hi = mid;
+            }
+            sg = lo;
+            return wseg[lo] + (q - woff[lo]);
+        };
+        const int cap = B.stage_cap;
+        // stage window offsets [q0, q0 + cnt) into LDS; returns sum of max|a|
+        auto stage_round = [&](int q0, int cnt) -> float {
+            float part = 0.0f;
+            for (int i = tid; i < cnt; i += kScatterBlock) {
+                int sg;
+                const int g = record_of(q0 + i, sg);
+                const float4 qa = rec[2 * (int64_t)g];
+                const float4 qb = rec[2 * (int64_t)g + 1];
+                const int r = sg >> 1;
+                const int wy = r % WY;
+                int d0 = (int)(__float_as_uint(qa.w) & 2047u) - o0;
+                if (d0 > e0 - 1 - mlo0) d0 -= Nx;
+                if (d0 < -mhi0) d0 += Nx;
+                const int pk = (d0 + 512) | (wy << 10);
+                stage[2 * i] = make_float4(qa.x, qa.y, qa.z, __int_as_float(pk));
+                stage[2 * i + 1] = qb;
+                part += fmaxf(fabsf(qb.x), fmaxf(fabsf(qb.y), fabsf(qb.z)));
+            }
+            return part;
+        };
+        // ---- amplitude bound of the tile (fixed-order reduction)
+        float part = 0.0f;
+        int q0 = 0;
+        if (wtot <= cap) {
+            part = stage_round(0, wtot);
+        } else {
+            for (int q = tid; q < wtot; q += kScatterBlock) {
+                int sg;
+                const float4 qb = rec[2 * (int64_t)record_of(q, sg) + 1];
                 part += fmaxf(fabsf(qb.x), fmaxf(fabsf(qb.y), fabsf(qb.z)));
             }
         }
-    }
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-    if ((tid & 63) == 0) s_part[tid >> 6] = part;
-    __syncthreads();
-    if (tid == 0) {
-        float bound = 0.0f;
-        for (int w = 0; w < kScatterBlock / 64; ++w) bound += s_part[w];
-        s_scale = (bound > 0.0f && bound < 3.0e38f) ? 1073741824.0f / bound : 1.0f;
-    }
-    __syncthreads();
-    const float scale = s_scale;
-    if (ncb > 0) {
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+        if (lane == 0) s_part[wv] = part;
+        __syncthreads();
+        if (tid == 0) {
+            float bound = 0.0f;
+            for (int w = 0; w < kScatterWaves; ++w) bound += s_part[w];
+            s_scale = (bound > 0.0f && bound < 3.0e38f) ? 1073741824.0f / bound : 1.0f;
+        }
+        __syncthreads();
+        scale = s_scale;
         const int64_t slot = (n - M) % (M + 1);
-        const float cut = B.R2f + B.guard;
-        const float hx = B.dxf[0];
+        const float hx = B.dxf[0], hy = B.dxf[1], hz = B.dxf[2];
         const float c = B.cexp;
         const float qx = exp2f(-2.0f * c * hx * hx);
-        // ---- pass B: stage visits in rounds, one lane per visit.  The cursor
-        // (k = bin, r = record) is uniform across the block; s_nvis is read by
-        // every thread before any thread appends (barrier in between).
-        int k = 0;
-        int64_t gb0 = bin_of(0);
-        int r = start[gb0], re = start[gb0 + 1];
-        while (true) {
-            while (k < ncb) {
-                if (r >= re) {
-                    if (++k >= ncb) break;
-                    const int64_t gb = bin_of(k);
-                    r = start[gb];
-                    re = start[gb + 1];
-                    continue;
-                }
-                const int nv0 = s_nvis;
-                __syncthreads();
-                // a chunk of c records adds at most c visits
-                const int room = kVisCap - nv0;
-                if (room < 64) break;
-                const int chunk = min(min(re - r, kScatterBlock), room);
-                if (tid < chunk) {
-                    const int rr = r + tid;
-                    const float4 qa = rec[2 * (int64_t)rr];
-                    int d0, d1, d2;
-                    if (locate(qa, d0, d1, d2)) {
-                        const float4 qb = rec[2 * (int64_t)rr + 1];
-                        const int slotv = atomicAdd(&s_nvis, 1);
-                        Visit v;
-                        v.phx = qa.x;
-                        v.phy = qa.y;
-                        v.phz = qa.z;
-                        v.ax = qb.x * scale;
-                        v.ay = qb.y * scale;
-                        v.az = qb.z * scale;
-                        v.dl = pack_dl(d0, d1, d2);
-                        v.pid = __float_as_int(qb.w);
-                        vis[slotv] = v;
-                        const int vol = (min(B.mhi[0], e0 - 1 - d0) - max(B.mlo[0], -d0) + 1) *
-                                        (min(B.mhi[1], e1 - 1 - d1) - max(B.mlo[1], -d1) + 1) *
-                                        (min(B.mhi[2], e2 - 1 - d2) - max(B.mlo[2], -d2) + 1);
-                        const int bk = work_bucket(vol);
-                        vkey[slotv] = (bk << 16) | atomicAdd(&s_bcnt[bk], 1);
-                    }
-                }
-                r += chunk;
+        bool staged = wtot <= cap;
+        while (q0 < wtot) {
+            const int cnt = min(cap, wtot - q0);
+            if (!staged) {
+                (void)stage_round(q0, cnt);
                 __syncthreads();
             }
-            __syncthreads();
-            const int nv = s_nvis;
-            if (nv == 0) break;
-            // order the staged visits by work, largest first, so that the 64 lanes of
-            // a wave walk stencils of similar size
-            if (tid == 0) {
-                int run = 0;
-                for (int b = kVisBuckets - 1; b >= 0; --b) {
-                    s_boff[b] = run;
-                    run += s_bcnt[b];
-                }
-            }
-            __syncthreads();
-            for (int vi = tid; vi < nv; vi += kScatterBlock) {
-                const int key = vkey[vi];
-                vperm[s_boff[key >> 16] + (key & 0xffff)] = vi;
-            }
-            __syncthreads();
-            if (tid < kVisBuckets) s_bcnt[tid] = 0;
-            for (int vs = tid; vs < nv; vs += kScatterBlock) {
-                const Visit v = vis[vperm[vs]];
-                const int dl0 = (v.dl & 1023) - 512, dl1 = ((v.dl >> 10) & 1023) - 512,
-                          dl2 = ((v.dl >> 20) & 1023) - 512;
-                const int c0lo = max(B.mlo[0], -dl0), c0hi = min(B.mhi[0], e0 - 1 - dl0);
-                const int c1lo = max(B.mlo[1], -dl1), c1hi = min(B.mhi[1], e1 - 1 - dl1);
-                const int c2lo = max(B.mlo[2], -dl2), c2hi = min(B.mhi[2], e2 - 1 - dl2);
-                for (int mz = c2lo; mz <= c2hi; ++mz) {
-                    const float tzv = d1(mz, v.phz, B.dxf[2]);
-                    const float tz2 = tzv * tzv;
-                    if (tz2 > cut) continue;
-                    const float gz = exp2f(-tz2 * c);
-                    // y-range of this plane's disk (superset; rows are settled exactly below)
-                    const float sy = sqrtf(fmaxf(cut - tz2, 0.0f)) / B.dxf[1];
-                    const int ylo = max(c1lo, (int)ceilf(v.phy - sy) - 1);
-                    const int yhi = min(c1hi, (int)floorf(v.phy + sy) + 1);
-                    for (int my = ylo; my <= yhi; ++my) {
-                        const float tyv = d1(my, v.phy, B.dxf[1]);
-                        const float ryz = fmaf(tyv, tyv, tz2);
-                        if (ryz > cut) continue;
-                        int lo, hi;
-                        row_range(v.phx, ryz, B, &B, slot, v.pid, my, mz, lo, hi);
-                        lo = max(lo, c0lo);
-                        hi = min(hi, c0hi);
-                        if (lo > hi) continue;
-                        const float gyz = exp2f(-(tyv * tyv) * c) * gz;
-                        const float t0 = ((float)lo - v.phx) * hx;
-                        float w = exp2f(-(t0 * t0) * c) * gyz;
-                        float rr = exp2f(-c * hx * fmaf(2.0f, t0, hx));
-                        uint32_t *ap =
-                            (uint32_t *)&acc[3 * ((mz + dl2) * PL + (my + dl1) * PX + dl0 + lo)];
-                        for (int m = lo; m <= hi; ++m) {
-                            atomicAdd(ap, fixed32(v.ax * w));
-                            atomicAdd(ap + 1, fixed32(v.ay * w));
-                            atomicAdd(ap + 2, fixed32(v.az * w));
-                            w *= rr;
-                            rr *= qx;
-                            ap += 3;
-                        }
+            staged = false;
+            for (int ci = wv; ci < ncls; ci += kScatterWaves) {
+                const int cl = s_cls[ci];
+                const int dy = mlo1 + cl % ny, dz = mlo2 + cl / ny;
+                // staged ranges of this class, one per tile plane lz < e2
+                int len = 0, sa = 0;
+                if (lane < e2) {
+                    const int ra = (lane + mhi2 - dz) * WY + (mhi1 - dy);
+                    const int a = max(woff[2 * ra], q0);
+                    const int b = min(woff[2 * (ra + e1)], q0 + cnt);
+                    if (b > a) {
+                        len = b - a;
+                        sa = a - q0;
                     }
                 }
+                const int incl = wave_incl_scan(len);
+                const int total = __shfl(incl, 63, 64);
+                if (lane < e2) {
+                    s_pre[wv][lane] = incl - len;
+                    s_sa[wv][lane] = sa;
+                }
+                if (lane == 0) s_pre[wv][e2] = total;
+                wave_sync_lds();
+                for (int q = lane; q < total; q += 64) {
+                    int lz = 0, hi = e2;
+                    while (hi - lz > 1) {
+                        const int mid = (lz + hi) >> 1;
+                        if (s_pre[wv][mid] <= q) lz = mid; else hi = mid;
+                    }
+                    const int i = s_sa[wv][lz] + (q - s_pre[wv][lz]);
+                    const float4 qa = stage[2 * i];
+                    const float4 qb = stage[2 * i + 1];
+                    const int pk = __float_as_int(qa.w);
+                    const int d0 = (pk & 1023) - 512;
+                    const int y = ((pk >> 10) & 1023) + dy - mhi1;
+                    const float tyv = d1(dy, qa.y, hy);
+                    const float tzv = d1(dz, qa.z, hz);
+                    const float ryz = fmaf(tyv, tyv, tzv * tzv);
+                    if (ryz > cut) continue;
+                    int rlo, rhi;
+                    row_range(qa.x, ryz, B, &B, slot, __float_as_int(qb.w), dy, dz, rlo, rhi);
+                    rlo = max(rlo, -d0);
+                    rhi = min(rhi, e0 - 1 - d0);
+                    if (rlo > rhi) continue;
+                    const float t0 = ((float)rlo - qa.x) * hx;
+                    float w = exp2f(-fmaf(t0, t0, ryz) * c);
+                    float rr = exp2f(-c * hx * fmaf(2.0f, t0, hx));
+                    const float ax = qb.x * scale, ay = qb.y * scale, az = qb.z * scale;
+                    uint32_t *ap = (uint32_t *)&acc[3 * ((lz * B.T[1] + y) * PX + d0 + rlo)];
+                    for (int m = rlo; m <= rhi; ++m) {
+                        atomicAdd(ap, fixed32(ax * w));
+                        atomicAdd(ap + 1, fixed32(ay * w));
+                        atomicAdd(ap + 2, fixed32(az * w));
+                        w *= rr;
+                        rr *= qx;
+                        ap += 3;
+                    }
+                }
+                wave_sync_lds();
             }
             __syncthreads();
-            if (tid == 0) s_nvis = 0;
-            __syncthreads();
-            if (k >= ncb) break;
+            q0 += cnt;
         }
     }
     __syncthreads();
@@ -525,8 +569,9 @@ __global__ void __launch_bounds__(kBlock) k_bin_pos_count(const DevBox *__restri
     int b[3];
     double ph;
     for (int d = 0; d < 3; ++d) cell_of(pos[d * np + p], B.L[d], B.dx[d], B.n[d], b[d], ph);
-    key[p] = (int32_t)(((int64_t)b[2] * B.n[1] + b[1]) * B.n[0] + b[0]);
-    rank[B.poff + p] = atomicAdd(&count[B.bin_off + tile_of(B, b[0], b[1], b[2])], 1);
+    const int64_t k = cell_key(B, b[0], b[1], b[2]);
+    key[p] = (int32_t)k;
+    rank[B.poff + p] = atomicAdd(&count[B.cell_off + k], 1);
 }
 
 __global__ void __launch_bounds__(kBlock) k_bin_pos_place(const DevBox *__restrict__ Bs, int ibox,
@@ -537,23 +582,24 @@ __global__ void __launch_bounds__(kBlock) k_bin_pos_place(const DevBox *__restri
     const DevBox &B = Bs[ibox];
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= B.np) return;
-    const int32_t k = key[p];
-    const int b0 = k % B.n[0];
-    const int b1 = (k / B.n[0]) % B.n[1];
-    const int b2 = k / (B.n[0] * B.n[1]);
-    perm[start[tile_of(B, b0, b1, b2)] + rank[B.poff + p]] = (int32_t)p;
+    perm[start[key[p]] + rank[B.poff + p]] = (int32_t)p;
 }
 
 }  // namespace
 
+hipError_t scan_counts(int32_t *count, int64_t n, int32_t *start, int32_t *part, hipStream_t st) {
+    const int64_t nchunk = (n + kScanChunk - 1) / kScanChunk;
+    if (nchunk == 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nchunk), dim3(256), 0, st, count, n, part);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, part, nchunk);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nchunk), dim3(256), 0, st, count, n, part,
+                       nchunk, start);
+    return hipGetLastError();
+}
+
 hipError_t fast_prepare_lds(size_t bytes) {
     return hipFuncSetAttribute((const void *)k_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)bytes);
-}
-
-size_t scatter_lds_bytes(const int32_t tile[3]) {
-    const size_t cs = 3 * (size_t)tile[2] * tile[1] * (tile[0] + 1);
-    return sizeof(int32_t) * (cs + (cs & 1)) + (sizeof(Visit) + 2 * sizeof(int)) * kVisCap;
 }
 
 hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
@@ -564,14 +610,12 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                                    P->dbox, P->nbox, P->s.step, P->M, P->s.count, P->s.rank);
             break;
         case 1:
-            hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, P->s.count, P->s.start,
-                               P->nbins_total, P->s.binmax);
-            break;
+            return scan_counts(P->s.count, P->ncell_total, P->s.start, P->s.part, st);
         case 2:
             if (P->np_total > 0)
                 hipLaunchKernelGGL(k_eval, dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step, P->M, P->s.start, P->s.rank,
-                                   P->s.rec, P->s.binmax);
+                                   P->s.rec);
             break;
         case 3:
             hipLaunchKernelGGL(k_scatter, dim3((unsigned)P->tblocks), dim3(kScatterBlock),
@@ -610,13 +654,15 @@ hipError_t fast_gather(erpp_plan *P, double *u_p, hipStream_t st) {
 hipError_t fast_bin_positions(erpp_plan *P, int ibox, const double *pos, int32_t *key,
                               int32_t *perm, int32_t *bin_start, hipStream_t st) {
     const DevBox &H = P->hbox[ibox];
-    const int64_t nb = (int64_t)H.ntile[0] * H.ntile[1] * H.ntile[2];
+    const int64_t nc = (int64_t)H.n[0] * H.n[1] * H.n[2];
     const unsigned blocks = (unsigned)((H.np + kBlock - 1) / kBlock);
     if (H.np > 0)
         hipLaunchKernelGGL(k_bin_pos_count, dim3(blocks), dim3(kBlock), 0, st, P->dbox, ibox, pos,
                            key, P->s.count, P->s.rank);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, P->s.count + H.bin_off, bin_start, nb,
-                       (uint32_t *)nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = scan_counts(P->s.count + H.cell_off, nc, bin_start, P->s.part, st);
+    if (e != hipSuccess) return e;
     if (H.np > 0)
         hipLaunchKernelGGL(k_bin_pos_place, dim3(blocks), dim3(kBlock), 0, st, P->dbox, ibox, key,
                            bin_start, P->s.rank, perm);

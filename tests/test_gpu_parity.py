@@ -157,13 +157,12 @@ def test_bin_keys_exact_and_grouping(shape, tile):
     assert start[0] == 0 and start[-1] == box.np_ and np.all(np.diff(start) >= 0)
     assert np.array_equal(np.sort(perm), np.arange(box.np_))
     Nx, Ny, Nz = shape
-    T = [min(tile[d], shape[d] - 10) for d in range(3)]
-    nt = [-(-shape[d] // T[d]) for d in range(3)]
-    assert nb == nt[0] * nt[1] * nt[2]
-    i, j, k = key % Nx, (key // Nx) % Ny, key // (Nx * Ny)
-    tid = ((k // T[2]) * nt[1] + j // T[1]) * nt[0] + i // T[0]
-    for b in range(nb):
-        assert np.all(tid[perm[start[b]:start[b + 1]]] == b)
+    assert nb == Nx * Ny * Nz
+    counts = np.bincount(ko, minlength=nb)
+    assert np.array_equal(np.diff(start), counts)
+    # every particle sits in the group of its own cell
+    grp = np.repeat(np.arange(nb), counts)
+    assert np.array_equal(ko[perm], grp)
 
 
 # ----------------------------------------------------------------- step ----
