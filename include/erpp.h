@@ -106,19 +106,18 @@ erpp_status erpp_plan_create(erpp_plan **plan, const erpp_box *boxes, int32_t nb
                              int32_t M, double dt, erpp_precision precision,
                              int32_t self_correction, void *stream);
 
-/* Scatter tile shape (nodes per tile in x, y, z) of an ERPP_F32_FAST plan.
- * Each entry in [4, 64] and tile_x * tile_y * tile_z <= 8192.  Per box the tile
- * is clipped so that a stencil never wraps onto a tile twice.  The tile must fit
- * the scatter's LDS for every box of the plan: an int32 copy of the tile
- * (12 bytes per node, rows padded by one node), the list of the tile's particle
- * window (two ints per cell-row segment, at most 1024 cell rows
- * (tile_y + S_y - 1)(tile_z + S_z - 1), S = stencil width in nodes) and at least
- * 256 staged particle records of 32 bytes, within 150 KiB; otherwise
- * ERPP_EINVAL and the plan keeps its tile.  Invalidates a captured graph. */
+/* Scatter pencil of an ERPP_F32_FAST plan: one workgroup owns all Nx nodes of
+ * tile[1] x tile[2] grid rows (y, z).  tile[0] is ignored (stored as 0: a pencil
+ * always spans the box in x); tile[1] in [1, 64], tile[2] in [1, 8].  Per box
+ * the pencil is clipped so that a stencil never wraps onto it twice.  The LDS
+ * copy of the pencil (12 bytes per node, rows unwrapped by the stencil width)
+ * plus the window's record table must fit 150 KiB for every box of the plan;
+ * otherwise ERPP_EINVAL and the plan keeps its pencil.  Invalidates a captured
+ * graph. */
 erpp_status erpp_plan_set_tile(erpp_plan *plan, const int32_t tile[3]);
 erpp_status erpp_plan_get_tile(const erpp_plan *plan, int32_t tile[3]);
 
-/* Autotuner (ERPP_F32_FAST): times every candidate tile shape on the plan's own
+/* Autotuner (ERPP_F32_FAST): times every candidate pencil shape on the plan's own
  * boxes (scatter of the current ring contents, which are only read) and keeps
  * the fastest.  With cache_path != NULL the choice is read from / appended to
  * that text file, keyed by the geometry; a hit skips the timing.  Synchronises

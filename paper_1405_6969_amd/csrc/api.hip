@@ -105,12 +105,11 @@ erpp_status alloc_bins(erpp_plan *p) {
 
 erpp_status check_tile(const int32_t tile[3]) {
     if (!tile) return fail(ERPP_EINVAL, "tile is NULL");
-    for (int d = 0; d < 3; ++d)
-        if (tile[d] < 4 || tile[d] > erpp::kMaxTileDim)
-            return fail(ERPP_EINVAL, "tile[%d]=%d outside [4, %d]", d, tile[d], erpp::kMaxTileDim);
-    if ((int64_t)tile[0] * tile[1] * tile[2] > erpp::kMaxTileVol)
-        return fail(ERPP_EINVAL, "tile volume %lld > %d",
-                    (long long)tile[0] * tile[1] * tile[2], erpp::kMaxTileVol);
+    if (tile[0] < 0) return fail(ERPP_EINVAL, "tile[0]=%d < 0", tile[0]);
+    if (tile[1] < 1 || tile[1] > erpp::kMaxTileY)
+        return fail(ERPP_EINVAL, "tile[1]=%d outside [1, %d]", tile[1], erpp::kMaxTileY);
+    if (tile[2] < 1 || tile[2] > erpp::kMaxTileZ)
+        return fail(ERPP_EINVAL, "tile[2]=%d outside [1, %d]", tile[2], erpp::kMaxTileZ);
     return ERPP_OK;
 }
 
@@ -145,16 +144,17 @@ hipError_t advance_step(erpp_plan *p, hipStream_t st) {
 
 static int32_t round4(int64_t v) { return (int32_t)((v + 3) & ~int64_t(3)); }
 
-// Tiles, block offsets and the scatter's LDS layout of every box for the plan's
-// tile.  Returns false when the tile does not fit (window rows or LDS).
+// Pencils, block offsets and the scatter's LDS layout of every box for the
+// plan's tile.  Returns false when a pencil does not fit the LDS.
 bool fill_box_tiles(erpp_plan *p) {
     int64_t cell = 0, bp = 0, bt = 0, br = 0;
-    int64_t fixed_max = 0;
-    bool ok = true;
+    int64_t lds_max = 0;
     for (auto &B : p->hbox) {
         int32_t ext[3];
-        for (int d = 0; d < 3; ++d) {
-            ext[d] = B.mhi[d] - B.mlo[d] + 1;
+        for (int d = 0; d < 3; ++d) ext[d] = B.mhi[d] - B.mlo[d] + 1;
+        B.T[0] = B.n[0];
+        B.ntile[0] = 1;
+        for (int d = 1; d < 3; ++d) {
             int32_t T = std::min(p->tile[d], B.n[d] - ext[d]);
             if (T < 1) T = 1;
             B.T[d] = T;
@@ -165,31 +165,24 @@ bool fill_box_tiles(erpp_plan *p) {
         B.blk_p = bp;
         bp += (B.np + kBlock - 1) / kBlock;
         B.blk_t = bt;
-        bt += (int64_t)B.ntile[0] * B.ntile[1] * B.ntile[2];
+        bt += (int64_t)B.ntile[1] * B.ntile[2];
         B.rows = (int64_t)(B.mhi[1] - B.mlo[1] + 1) * (B.mhi[2] - B.mlo[2] + 1);
         B.blk_r = br;
         br += (B.np * B.rows + kBlock - 1) / kBlock;
-        // scatter LDS: int32 tile [3][T2][T1][T0+1], window offsets [2 rows + 1],
-        // segment starts [2 rows], staged records (2 float4 each)
-        const int64_t wrows = (int64_t)(B.T[1] + ext[1] - 1) * (B.T[2] + ext[2] - 1);
-        if (wrows > kMaxWinRows) ok = false;
-        B.wrows = (int32_t)std::min<int64_t>(wrows, kMaxWinRows);
-        const int64_t accw = 3 * (int64_t)B.T[2] * B.T[1] * (B.T[0] + 1);
-        B.lds_woff = round4(accw);
-        B.lds_wseg = B.lds_woff + round4(2 * wrows + 1);
-        B.lds_stage = (B.lds_wseg + round4(2 * wrows)) / 4;
-        fixed_max = std::max<int64_t>(fixed_max, 16 * (int64_t)B.lds_stage);
+        // scatter LDS: int32 pencil [T2][T1][pxa][3], then the window's record-start
+        // table [(T2 + ext2 - 1)][(T1 + ext1 - 1) + 2]
+        B.pxa = B.n[0] + ext[0];
+        const int64_t accw = 3 * (int64_t)B.T[2] * B.T[1] * B.pxa;
+        B.lds_tab = round4(accw);
+        const int64_t tabw = (int64_t)(B.T[2] + ext[2] - 1) * (B.T[1] + ext[1] + 1);
+        lds_max = std::max<int64_t>(lds_max, 4 * (B.lds_tab + round4(tabw)));
     }
-    int64_t cap = ((int64_t)kScatterLdsTarget - fixed_max) / 32;
-    cap = std::max<int64_t>(kMinStage, std::min<int64_t>(kMaxStage, cap));
-    for (auto &B : p->hbox) B.stage_cap = (int32_t)cap;
     p->ncell_total = cell;
     p->pblocks = bp;
     p->tblocks = bt;
     p->pblocks_rows = br;
-    p->lds_bytes = (size_t)(fixed_max + 32 * cap);
-    if (p->lds_bytes > kMaxScatterLds) ok = false;
-    return ok;
+    p->lds_bytes = (size_t)lds_max;
+    return p->lds_bytes <= kMaxScatterLds;
 }
 
 }  // namespace erpp
@@ -280,6 +273,7 @@ erpp_status erpp_plan_create(erpp_plan **out, const erpp_box *boxes, int32_t nbo
         B.s2sf = (float)B.s2s;
         B.preff = (float)B.pref;
         B.rhof_inv = (float)(1.0 / X.rho_f);
+        B.idxf0 = (float)(1.0 / B.dx[0]);
         B.x = X.x;
         B.v = X.v;
         B.ring_x = X.ring_x;
@@ -302,8 +296,8 @@ erpp_status erpp_plan_create(erpp_plan **out, const erpp_box *boxes, int32_t nbo
     p->hbox = hb;
     p->np_total = np_total;
     if (!erpp::fill_box_tiles(p)) {
-        // the default tile is too large for these stencils: fall back to the smallest
-        for (int d = 0; d < 3; ++d) p->tile[d] = 4;
+        // the default pencil is too large for these boxes: fall back to the thinnest
+        p->tile[1] = p->tile[2] = 1;
         if (!erpp::fill_box_tiles(p)) {
             delete p;
             return fail(ERPP_EUNSUPPORTED, "stencil too wide for the scatter's LDS tile");
@@ -342,14 +336,14 @@ erpp_status erpp_plan_set_tile(erpp_plan *p, const int32_t tile[3]) {
     int32_t old[3];
     for (int d = 0; d < 3; ++d) {
         old[d] = p->tile[d];
-        p->tile[d] = tile[d];
+        p->tile[d] = d == 0 ? 0 : tile[d];
     }
     if (!erpp::fill_box_tiles(p)) {
         const size_t need = p->lds_bytes;
         for (int d = 0; d < 3; ++d) p->tile[d] = old[d];
         erpp::fill_box_tiles(p);
-        return fail(ERPP_EINVAL, "tile %dx%dx%d does not fit the scatter's LDS (%zu bytes, "
-                    "window rows <= %d)", tile[0], tile[1], tile[2], need, erpp::kMaxWinRows);
+        return fail(ERPP_EINVAL, "pencil %d x %d does not fit the scatter's LDS (%zu bytes)",
+                    tile[1], tile[2], need);
     }
     drop_graph(p);
     return upload_boxes(p);
@@ -460,7 +454,7 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
     hipStream_t st = as_stream(stream);
     // geometry key
     std::ostringstream key;
-    key << "v2 M" << p->M << " nbox" << p->nbox;
+    key << "v3 M" << p->M << " nbox" << p->nbox;
     for (const auto &B : p->hbox)
         key << " " << B.n[0] << "x" << B.n[1] << "x" << B.n[2] << ":" << B.np << ":" << B.mlo[0]
             << "," << B.mhi[0];
@@ -477,9 +471,9 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
                 return erpp_plan_set_tile(p, t);
         }
     }
-    static const int32_t cand[][3] = {{64, 8, 8},  {32, 8, 8},   {64, 8, 4},  {64, 4, 8},
-                                      {32, 16, 8}, {32, 8, 16},  {16, 16, 16}, {16, 8, 8},
-                                      {32, 4, 8},  {64, 16, 4},  {32, 16, 16}, {16, 16, 8}};
+    static const int32_t cand[][3] = {{0, 4, 4}, {0, 2, 2}, {0, 4, 2}, {0, 2, 4},
+                                      {0, 8, 2}, {0, 8, 4}, {0, 4, 8}, {0, 1, 2},
+                                      {0, 2, 1}, {0, 1, 1}, {0, 8, 8}, {0, 16, 2}};
     const int ncand = (int)(sizeof cand / sizeof cand[0]);
     int32_t best[3] = {p->tile[0], p->tile[1], p->tile[2]};
     float best_ms = 1e30f;

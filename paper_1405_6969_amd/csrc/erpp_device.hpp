@@ -96,36 +96,29 @@ __device__ __forceinline__ bool inside32(int mx, float phx, float ryz, const Dev
 }
 
 // Contiguous range [lo, hi] of x offsets of row (my, mz) inside the sphere,
-// within [mlo, mhi].  lo > hi when the row is empty.  A square-root estimate is
-// trusted when it is far from an integer and the row is not tiny; otherwise the
-// ends are settled node by node with inside32 (membership is monotone in |mx -
-// phi| along a row).  Deterministic in its inputs, so every kernel that calls it
-// sees the same node set.
+// within [mlo, mhi]; lo > hi when the row is empty.  The ends are estimated from
+// the row's half-width s = sqrt(R^2 - ryz) / dx (raw v_sqrt, multiply by 1/dx).
+// Against the exact boundary (FP32 rounding plus the FP64 guard band) its error
+// in nodes is about (guard + ulp(R^2)) / (2 s dx^2) <= 5e-5 R^2 / (s dx^2), well
+// under one node for s >= 0.01; a row with smaller s holds at most the node
+// nearest phi, which the tests on either side of the estimate reach.
+// Each end is then settled by the exact decision (inside32) at the estimate and
+// one node outward; membership is monotone in |mx - phi| along a row.  The node
+// set is therefore the exact one, the same in every kernel that calls this.
 __device__ __forceinline__ void row_range(float phx, float ryz, const DevBox &B,
                                           const DevBox *Bp, int64_t slot, int pid, int my,
                                           int mz, int &lo, int &hi) {
-    const int mlo = B.mlo[0], mhi = B.mhi[0];
-    float rem = B.R2f - ryz;
-    if (rem < -B.guard) { lo = 1; hi = 0; return; }
-    float s = sqrtf(fmaxf(rem, 0.0f)) / B.dxf[0];
-    float tl = phx - s, th = phx + s;
-    float cl = ceilf(tl), fh = floorf(th);
-    const float eps = 1.0e-4f;
-    bool trust = (s >= 0.5f) && (cl - tl > eps) && (tl - (cl - 1.0f) > eps) &&
-                 (th - fh > eps) && ((fh + 1.0f) - th > eps);
-    int l = (int)cl, h = (int)fh;
-    if (!trust) {
-        if (l < mlo) l = mlo;
-        if (h > mhi) h = mhi;
-        while (l - 1 >= mlo && inside32(l - 1, phx, ryz, B, Bp, slot, pid, my, mz)) --l;
-        while (l <= h && !inside32(l, phx, ryz, B, Bp, slot, pid, my, mz)) ++l;
-        while (h + 1 <= mhi && inside32(h + 1, phx, ryz, B, Bp, slot, pid, my, mz)) ++h;
-        while (h >= l && !inside32(h, phx, ryz, B, Bp, slot, pid, my, mz)) --h;
-    }
-    if (l < mlo) l = mlo;
-    if (h > mhi) h = mhi;
-    lo = l;
-    hi = h;
+    const float rem = fmaxf(B.R2f - ryz, 0.0f);
+    const float s = __builtin_amdgcn_sqrtf(rem) * B.idxf0;
+    int l = (int)ceilf(phx - s), h = (int)floorf(phx + s);
+    const bool in_lm = inside32(l - 1, phx, ryz, B, Bp, slot, pid, my, mz);
+    const bool in_l = inside32(l, phx, ryz, B, Bp, slot, pid, my, mz);
+    const bool in_h = inside32(h, phx, ryz, B, Bp, slot, pid, my, mz);
+    const bool in_hp = inside32(h + 1, phx, ryz, B, Bp, slot, pid, my, mz);
+    l = in_lm ? l - 1 : (in_l ? l : l + 1);
+    h = in_hp ? h + 1 : (in_h ? h : h - 1);
+    lo = max(l, B.mlo[0]);
+    hi = min(h, B.mhi[0]);
 }
 
 // ---------------------------------------------------------- self-disturbance --

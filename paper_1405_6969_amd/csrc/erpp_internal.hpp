@@ -11,15 +11,12 @@
 
 namespace erpp {
 
-constexpr int kMaxTileDim = 64;
-constexpr int kMaxTileVol = 8192;
+constexpr int kMaxTileY = 64;        // scatter pencil: T1 x T2 nodes in (y, z), all of x
+constexpr int kMaxTileZ = 8;
 constexpr int kBlock = 256;          // threads per block of particle kernels
 constexpr int kScatterBlock = 512;   // threads per block of the tiled scatter
 constexpr int kScatterWaves = kScatterBlock / 64;
 constexpr int kScanChunk = 4096;     // counters per block of the device-wide scan
-constexpr int kMaxWinRows = 1024;    // cell rows of a scatter tile's particle window
-constexpr int kMinStage = 256;       // smallest staging buffer (records) of a scatter round
-constexpr int kMaxStage = 4096;
 
 // Everything a kernel needs to know about one box; lives in device memory as
 // an array indexed by box.  Plain old data.
@@ -27,13 +24,10 @@ struct DevBox {
     int32_t n[3];        // nodes
     int32_t mlo[3];      // stencil offsets m in [mlo, mhi] around the base cell
     int32_t mhi[3];
-    int32_t T[3];        // scatter tile (nodes) of this box, clipped
-    int32_t ntile[3];    // tiles per dimension
-    int32_t wrows;       // cell rows (y, z) of a tile's particle window
-    int32_t lds_woff;    // LDS word offsets: window offsets, segment starts, staged records
-    int32_t lds_wseg;
-    int32_t lds_stage;   // (in 16-byte units)
-    int32_t stage_cap;   // records staged per round
+    int32_t T[3];        // scatter pencil (nodes) of this box: T[0] = Nx, T[1], T[2] clipped
+    int32_t ntile[3];    // pencils per dimension (ntile[0] = 1)
+    int32_t pxa;         // words per unwrapped pencil row in LDS (Nx + mhi - mlo + 1)
+    int32_t lds_tab;     // LDS word offset of the window's record-start table
     int64_t np;          // particles
     int64_t poff;        // first particle in the concatenated particle space
     int64_t cell_off;    // first cell of this box in the concatenated cell-key space
@@ -55,7 +49,7 @@ struct DevBox {
     float cexp;          // 1 / (2 sigma^2 ln 2): raw weight = exp2(-d2 cexp)
     float s2sf, preff;
     float rhof_inv;
-    float pad1;
+    float idxf0;         // 1 / dx (FP32), row-end estimates
     double *x, *v, *ring_x;
     void *ring_d;
     const float *tau;
@@ -87,7 +81,7 @@ struct erpp_plan {
     double dt = 0;
     erpp_precision prec = ERPP_F32_FAST;
     int32_t self_correction = 1;
-    int32_t tile[3] = {16, 16, 16};
+    int32_t tile[3] = {0, 4, 4};     // scatter pencil: [0] unused (all of x), T1, T2
     std::vector<erpp_box> boxes;
     std::vector<erpp::DevBox> hbox;
     erpp::DevBox *dbox = nullptr;

@@ -7,10 +7,10 @@
 //   k_eval        per particle: FP64 cell/offset of X^{n-M}, FP32 Gaussian
 //                 normalisation over the 3-sigma sphere, record
 //                 {offsets, amplitude} written at its cell-sorted slot
-//   k_scatter     one workgroup per tile of nodes: the stencil rows of every
-//                 particle that reaches the tile are accumulated into an LDS
-//                 copy of the tile, which is then stored (each node written
-//                 once, no global atomics)
+//   k_scatter     one workgroup per pencil of nodes (full x extent): the
+//                 stencil rows of every particle that reaches the pencil are
+//                 accumulated into an LDS copy of it, which is then stored (each
+//                 node written once, no global atomics)
 //   k_update      per particle: trilinear carrier, closed-form self term,
 //                 Stokes drag, history write, explicit Euler, wrap
 #include <hip/hip_runtime.h>
@@ -224,41 +224,43 @@ __device__ __forceinline__ int wrap_index(int i, int N) {
     return i < 0 ? i + N : i;
 }
 
-// Contribution to the integer tile: round to the nearest int32 (|v| < 2^30 by
-// the choice of scale; the error of one term is at most half a unit).
-__device__ __forceinline__ uint32_t fixed32(float v) { return (uint32_t)__float2int_rn(v); }
-
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// Contribution to the integer tile: v_cvt_rpi_i32_f32 rounds to floor(v + 0.5)
+// in one instruction (|v| < 2^30 by the choice of scale; the error of one term
+// is at most half a unit; ties, which round up, have measure zero).
+__device__ __forceinline__ uint32_t fixed32(float v) {
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+    return (uint32_t)r;
 }
 
-// One workgroup per tile of nodes (owner computes: every node of the tile is
-// written once, by this workgroup; no global atomics).
-//
-// Window.  The particles whose stencil can reach the tile have their base cell
-// in the tile grown by the stencil extent.  Records are sorted by cell, so the
-// window is one contiguous record range per (cell row y, z, x-part) -- a
-// "segment"; at most two x-parts when the window wraps in x.  The segments are
-// listed in window order (z, y, x-part); the window offset of a record is its
-// position in that concatenation.
+constexpr int kMaxRanges = 2 * kMaxTileZ;   // record ranges of one row class (two per plane)
+
+// One workgroup per pencil of nodes: the whole x extent of the box times
+// T1 x T2 nodes in (y, z).  Owner computes: every node of the pencil is written
+// once, by this workgroup; no global atomics.
 //
 // Row classes.  Every stencil row of a particle is a relative offset (dy, dz)
-// from its base cell -- its class.  For class (dy, dz) the particles whose row
-// lies on tile plane z and inside the tile in y are those of e1 consecutive
-// window cell rows at fixed window z: one contiguous range of window offsets.
+// from its base cell (b0, b1, b2) -- its class.  For class (dy, dz) the
+// particles whose row lies on pencil plane z are those with b2 = o2 + z - dz and
+// b1 in [o1 - dy, o1 - dy + e1): since records are sorted by cell and a pencil
+// spans all of x, that is one contiguous record range (two when it wraps in y).
 // A wave takes a class and runs one lane per (particle, row) over the ranges of
-// all tile planes, so its 64 lanes walk rows of the same relative offset, whose
-// x extents differ by at most a node or two -- the inner node loop stays
-// converged.  Records are staged in LDS in rounds of window offsets.
+// all e2 planes, so its 64 lanes walk rows of the same relative offset, whose
+// lengths differ by at most a node or two, and no row is ever cut by the tile.
+// Records are read straight from the cell-sorted array (L2), one pass ahead of
+// use, so the loads overlap the previous pass's LDS atomics (they wait on a
+// different counter).
+//
+// The LDS tile keeps each pencil row unwrapped in x: a row's nodes b0 + m,
+// m in [mlo, mhi], sit at index b0 + m - mlo of a row of Nx + (mhi - mlo) + 1
+// words, and the store folds the ends back onto the periodic row.
 //
 // Accumulation is exact integer arithmetic: each contribution a*w is rounded to
-// an int32 with the per-tile scale 2^30 / A, where A = sum over the window of
-// max_c |amplitude| bounds |f| at every node of the tile (the raw Gaussian is
-// <= 1), and added with ds_add_u32 (the FP32 LDS atomic runs ~40x slower on
-// gfx950).  Integer additions commute, so the forcing does not depend on the
-// order of the adds.
+// an int32 with the per-pencil scale 2^30 / A, where A = sum over the pencil's
+// particle window of max_c |amplitude| bounds |f| at every node of the pencil
+// (the raw Gaussian is <= 1), and added with ds_add_u32 (the FP32 LDS atomic
+// runs ~40x slower on gfx950).  Integer additions commute, so the forcing does
+// not depend on the order of the adds.
 __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restrict__ Bs,
                                                            int nbox,
                                                            const int64_t *__restrict__ stepp,
@@ -266,9 +268,6 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
                                                            const int32_t *__restrict__ start,
                                                            const float4 *__restrict__ rec) {
     extern __shared__ int32_t lds[];
-    __shared__ int s_sw[kScatterWaves];
-    __shared__ int s_pre[kScatterWaves][65];
-    __shared__ int s_sa[kScatterWaves][64];
     __shared__ int s_cls[256];
     __shared__ int s_ncls;
     __shared__ float s_part[kScatterWaves];
@@ -276,37 +275,38 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
     const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_t; });
     const DevBox &B = Bs[bi];
     const int t = (int)(blockIdx.x - B.blk_t);
-    const int tx = t % B.ntile[0];
-    const int ty = (t / B.ntile[0]) % B.ntile[1];
-    const int tz = t / (B.ntile[0] * B.ntile[1]);
-    const int o0 = tx * B.T[0], o1 = ty * B.T[1], o2 = tz * B.T[2];
-    const int e0 = min(B.T[0], B.n[0] - o0);
-    const int e1 = min(B.T[1], B.n[1] - o1);
-    const int e2 = min(B.T[2], B.n[2] - o2);
-    const int PX = B.T[0] + 1;
-    const int PL = B.T[1] * PX;
-    const int CS = B.T[2] * PL;        // nodes of the padded tile; component c of node a at 3a+c
-    int32_t *acc = lds;
-    int *woff = lds + B.lds_woff;       // [nseg + 1] window offset of each segment
-    int *wseg = lds + B.lds_wseg;       // [nseg]     first record of each segment
-    float4 *stage = (float4 *)lds + B.lds_stage;   // [2 * stage_cap]
+    const int T1 = B.T[1], T2 = B.T[2];
+    const int o1 = (t % B.ntile[1]) * T1;
+    const int o2 = (t / B.ntile[1]) * T2;
+    const int Nx = B.n[0], Ny = B.n[1], Nz = B.n[2];
+    const int e1 = min(T1, Ny - o1);
+    const int e2 = min(T2, Nz - o2);
+    const int PXa = B.pxa;                 // words per unwrapped row (per component)
+    int32_t *acc = lds;                    // [T2][T1][PXa][3]
+    int *tab = lds + B.lds_tab;            // record-start table of the window
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int i = tid; i < 3 * CS; i += kScatterBlock) acc[i] = 0;
-    const int64_t n = *stepp;
     const int mlo0 = B.mlo[0], mhi0 = B.mhi[0];
     const int mlo1 = B.mlo[1], mhi1 = B.mhi[1];
     const int mlo2 = B.mlo[2], mhi2 = B.mhi[2];
+    for (int i = tid; i < 3 * T2 * T1 * PXa; i += kScatterBlock) acc[i] = 0;
+    const int64_t n = *stepp;
     float scale = 1.0f;
     if (n >= M) {
-        const int Nx = B.n[0], Ny = B.n[1], Nz = B.n[2];
-        const int WY = e1 + mhi1 - mlo1;
+        const int WY = e1 + mhi1 - mlo1;      // window cell rows in y, z
         const int WZ = e2 + mhi2 - mlo2;
-        const int nseg = 2 * WY * WZ;
-        const int xa = o0 - mhi0;                 // first base cell in x (unwrapped)
-        const int wx = e0 + mhi0 - mlo0;          // base cells in x (< Nx)
-        const float cut = B.R2f + B.guard;
+        const int TW = WY + 2;                // table row: WY + 1 row starts, then end of plane
+        // tab[wz][j] = first record of cell row b1 = (o1 - mhi1 + j) mod Ny of window
+        // plane b2 = (o2 - mhi2 + wz) mod Nz, j <= WY; tab[wz][WY + 1] = end of the plane
+        for (int k = tid; k < WZ * TW; k += kScatterBlock) {
+            const int wz = k / TW, j = k - wz * TW;
+            const int b2 = wrap_index(o2 - mhi2 + wz, Nz);
+            const int64_t plane = B.cell_off + (int64_t)b2 * Ny * Nx;
+            const int b1 = (j <= WY) ? wrap_index(o1 - mhi1 + j, Ny) : Ny;
+            tab[k] = start[plane + (int64_t)b1 * Nx];
+        }
         // row classes that some particle can reach: nearest approach of the row to
         // a base-cell offset in [0, 1)^2 within the cut-off
+        const float cut = B.R2f + B.guard;
         const int ny = mhi1 - mlo1 + 1, nz = mhi2 - mlo2 + 1;
         if (tid == 0) s_ncls = 0;
         __syncthreads();
@@ -316,86 +316,33 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
             const float az = (float)(dz >= 1 ? dz - 1 : -dz) * B.dxf[2];
             if (fmaf(ay, ay, az * az) <= cut) s_cls[atomicAdd(&s_ncls, 1)] = tid;
         }
-        // segment table: counts, then window offsets by a block scan
-        const int per = (nseg + kScatterBlock - 1) / kScatterBlock;
-        const int k0 = tid * per, k1 = min(k0 + per, nseg);
-        int mine = 0;
-        for (int k = k0; k < k1; ++k) {
-            const int r = k >> 1, j = k & 1;
-            const int wy = r % WY, wz = r / WY;
-            const int b1 = wrap_index(o1 - mhi1 + wy, Ny);
-            const int b2 = wrap_index(o2 - mhi2 + wz, Nz);
-            int lo, hi;
-            if (xa < 0) {
-                lo = j ? 0 : xa + Nx;
-                hi = j ? xa + wx - 1 : Nx - 1;
-            } else if (xa + wx > Nx) {
-                lo = j ? 0 : xa;
-                hi = j ? xa + wx - 1 - Nx : Nx - 1;
-            } else {
-                lo = j ? 0 : xa;
-                hi = j ? -1 : xa + wx - 1;
-            }
-            int gs = 0, c = 0;
-            if (lo <= hi) {
-                const int64_t base = B.cell_off + ((int64_t)b2 * Ny + b1) * Nx;
-                gs = start[base + lo];
-                c = start[base + hi + 1] - gs;
-            }
-            wseg[k] = gs;
-            woff[k] = c;
-            mine += c;
-        }
-        int wtot;
-        int run = block_excl_scan(mine, s_sw, kScatterWaves, &wtot);
-        for (int k = k0; k < k1; ++k) {
-            const int c = woff[k];
-            woff[k] = run;
-            run += c;
-        }
-        if (tid == 0) woff[nseg] = wtot;
         __syncthreads();
-        const int ncls = s_ncls;
-        // window offset -> (segment, record); woff[s] <= q < woff[s + 1]
-        auto record_of = [&](int q, int &sg) -> int {
-            int lo = 0, hi = nseg;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (woff[mid] <= q) lo = mid; else hi = mid;
+        // records of window plane wz, cell rows j in [ja, ja + len): [g0, g1) and,
+        // when the rows wrap past Ny, [h0, h1)
+        auto ranges = [&](int wz, int ja, int len, int &g0, int &g1, int &h0, int &h1) {
+            const int *T = tab + wz * TW;
+            const int b1a = wrap_index(o1 - mhi1 + ja, Ny);
+            g0 = T[ja];
+            if (b1a + len <= Ny) {
+                g1 = (b1a + len == Ny) ? T[WY + 1] : T[ja + len];
+                h0 = h1 = 0;
+            } else {
+                g1 = T[WY + 1];
+                h0 = T[ja + (Ny - b1a)];
+                h1 = T[ja + len];
             }
-            sg = lo;
-            return wseg[lo] + (q - woff[lo]);
         };
-        const int cap = B.stage_cap;
-        // stage window offsets [q0, q0 + cnt) into LDS; returns sum of max|a|
-        auto stage_round = [&](int q0, int cnt) -> float {
-            float part = 0.0f;
-            for (int i = tid; i < cnt; i += kScatterBlock) {
-                int sg;
-                const int g = record_of(q0 + i, sg);
-                const float4 qa = rec[2 * (int64_t)g];
+        // ---- amplitude bound of the pencil (fixed-order reduction)
+        float part = 0.0f;
+        for (int wz = 0; wz < WZ; ++wz) {
+            int g0, g1, h0, h1;
+            ranges(wz, 0, WY, g0, g1, h0, h1);
+            for (int g = g0 + tid; g < g1; g += kScatterBlock) {
                 const float4 qb = rec[2 * (int64_t)g + 1];
-                const int r = sg >> 1;
-                const int wy = r % WY;
-                int d0 = (int)(__float_as_uint(qa.w) & 2047u) - o0;
-                if (d0 > e0 - 1 - mlo0) d0 -= Nx;
-                if (d0 < -mhi0) d0 += Nx;
-                const int pk = (d0 + 512) | (wy << 10);
-                stage[2 * i] = make_float4(qa.x, qa.y, qa.z, __int_as_float(pk));
-                stage[2 * i + 1] = qb;
                 part += fmaxf(fabsf(qb.x), fmaxf(fabsf(qb.y), fabsf(qb.z)));
             }
-            return part;
-        };
-        // ---- amplitude bound of the tile (fixed-order reduction)
-        float part = 0.0f;
-        int q0 = 0;
-        if (wtot <= cap) {
-            part = stage_round(0, wtot);
-        } else {
-            for (int q = tid; q < wtot; q += kScatterBlock) {
-                int sg;
-                const float4 qb = rec[2 * (int64_t)record_of(q, sg) + 1];
+            for (int g = h0 + tid; g < h1; g += kScatterBlock) {
+                const float4 qb = rec[2 * (int64_t)g + 1];
                 part += fmaxf(fabsf(qb.x), fmaxf(fabsf(qb.y), fabsf(qb.z)));
             }
         }
@@ -413,92 +360,118 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
         const float hx = B.dxf[0], hy = B.dxf[1], hz = B.dxf[2];
         const float c = B.cexp;
         const float qx = exp2f(-2.0f * c * hx * hx);
-        bool staged = wtot <= cap;
-        while (q0 < wtot) {
-            const int cnt = min(cap, wtot - q0);
-            if (!staged) {
-                (void)stage_round(q0, cnt);
-                __syncthreads();
+        const int ncls = s_ncls;
+        const int nr = 2 * e2;
+        for (int ci = wv; ci < ncls; ci += kScatterWaves) {
+            const int cl = s_cls[ci];
+            const int dy = mlo1 + cl % ny, dz = mlo2 + cl / ny;
+            // lane k < 2 e2: part (k & 1) of the records of plane k >> 1
+            int len = 0, gb = 0;
+            if (lane < nr) {
+                int g0, g1, h0, h1;
+                ranges((lane >> 1) + mhi2 - dz, mhi1 - dy, e1, g0, g1, h0, h1);
+                gb = (lane & 1) ? h0 : g0;
+                len = (lane & 1) ? h1 - h0 : g1 - g0;
             }
-            staged = false;
-            for (int ci = wv; ci < ncls; ci += kScatterWaves) {
-                const int cl = s_cls[ci];
-                const int dy = mlo1 + cl % ny, dz = mlo2 + cl / ny;
-                // staged ranges of this class, one per tile plane lz < e2
-                int len = 0, sa = 0;
-                if (lane < e2) {
-                    const int ra = (lane + mhi2 - dz) * WY + (mhi1 - dy);
-                    const int a = max(woff[2 * ra], q0);
-                    const int b = min(woff[2 * (ra + e1)], q0 + cnt);
-                    if (b > a) {
-                        len = b - a;
-                        sa = a - q0;
-                    }
-                }
-                const int incl = wave_incl_scan(len);
-                const int total = __shfl(incl, 63, 64);
-                if (lane < e2) {
-                    s_pre[wv][lane] = incl - len;
-                    s_sa[wv][lane] = sa;
-                }
-                if (lane == 0) s_pre[wv][e2] = total;
-                wave_sync_lds();
-                for (int q = lane; q < total; q += 64) {
-                    int lz = 0, hi = e2;
-                    while (hi - lz > 1) {
-                        const int mid = (lz + hi) >> 1;
-                        if (s_pre[wv][mid] <= q) lz = mid; else hi = mid;
-                    }
-                    const int i = s_sa[wv][lz] + (q - s_pre[wv][lz]);
-                    const float4 qa = stage[2 * i];
-                    const float4 qb = stage[2 * i + 1];
-                    const int pk = __float_as_int(qa.w);
-                    const int d0 = (pk & 1023) - 512;
-                    const int y = ((pk >> 10) & 1023) + dy - mhi1;
-                    const float tyv = d1(dy, qa.y, hy);
-                    const float tzv = d1(dz, qa.z, hz);
-                    const float ryz = fmaf(tyv, tyv, tzv * tzv);
-                    if (ryz > cut) continue;
-                    int rlo, rhi;
-                    row_range(qa.x, ryz, B, &B, slot, __float_as_int(qb.w), dy, dz, rlo, rhi);
-                    rlo = max(rlo, -d0);
-                    rhi = min(rhi, e0 - 1 - d0);
-                    if (rlo > rhi) continue;
-                    const float t0 = ((float)rlo - qa.x) * hx;
-                    float w = exp2f(-fmaf(t0, t0, ryz) * c);
-                    float rr = exp2f(-c * hx * fmaf(2.0f, t0, hx));
-                    const float ax = qb.x * scale, ay = qb.y * scale, az = qb.z * scale;
-                    uint32_t *ap = (uint32_t *)&acc[3 * ((lz * B.T[1] + y) * PX + d0 + rlo)];
-                    for (int m = rlo; m <= rhi; ++m) {
-                        atomicAdd(ap, fixed32(ax * w));
-                        atomicAdd(ap + 1, fixed32(ay * w));
-                        atomicAdd(ap + 2, fixed32(az * w));
-                        w *= rr;
-                        rr *= qx;
-                        ap += 3;
-                    }
-                }
-                wave_sync_lds();
+            const int incl = wave_incl_scan(len);
+            const int total = __shfl(incl, 63, 64);
+            if (total == 0) continue;
+            // item q of range k is record q + off_k (pre_k <= q < pre_k + len_k)
+            const int pre = incl - len;
+            const int off = gb - pre;
+            int pre_k[kMaxRanges], off_k[kMaxRanges];
+#pragma unroll
+            for (int k = 0; k < kMaxRanges; ++k) {
+                pre_k[k] = __builtin_amdgcn_readlane(pre, k);
+                off_k[k] = __builtin_amdgcn_readlane(off, k);
             }
-            __syncthreads();
-            q0 += cnt;
+            auto record_of = [&](int q) -> int {
+                int o = off_k[0];
+#pragma unroll
+                for (int k = 1; k < kMaxRanges; ++k)
+                    if (k < nr) o = (q >= pre_k[k]) ? off_k[k] : o;
+                return q + o;
+            };
+            int q = lane;
+            float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na;
+            if (q < total) {
+                const int g = record_of(q);
+                na = rec[2 * (int64_t)g];
+                nb = rec[2 * (int64_t)g + 1];
+            }
+            while (q < total) {
+                const float4 qa = na, qb = nb;
+                const int qn = q + 64;
+                if (qn < total) {
+                    const int g = record_of(qn);
+                    na = rec[2 * (int64_t)g];
+                    nb = rec[2 * (int64_t)g + 1];
+                }
+                q = qn;
+                const uint32_t ijk = __float_as_uint(qa.w);
+                const int b0 = (int)(ijk & 2047u);
+                int y = (int)((ijk >> 11) & 2047u) + dy - o1;
+                int z = (int)(ijk >> 22) + dz - o2;
+                y += (y < 0) ? Ny : 0;
+                y -= (y >= Ny) ? Ny : 0;
+                z += (z < 0) ? Nz : 0;
+                z -= (z >= Nz) ? Nz : 0;
+                const float tyv = d1(dy, qa.y, hy);
+                const float tzv = d1(dz, qa.z, hz);
+                const float ryz = fmaf(tyv, tyv, tzv * tzv);
+                if (ryz > cut) continue;
+                int rlo, rhi;
+                row_range(qa.x, ryz, B, &B, slot, __float_as_int(qb.w), dy, dz, rlo, rhi);
+                if (rlo > rhi) continue;
+                // raw v_exp_f32: both arguments lie in [-2 R^2 c, 0], far from underflow
+                const float t0 = ((float)rlo - qa.x) * hx;
+                float w = __builtin_amdgcn_exp2f(-fmaf(t0, t0, ryz) * c);
+                float rr = __builtin_amdgcn_exp2f(-c * hx * fmaf(2.0f, t0, hx));
+                const float ax = qb.x * scale, ay = qb.y * scale, az = qb.z * scale;
+                const int row = (int)__umul24((unsigned)z, (unsigned)T1) + y;
+                const int node = (int)__umul24((unsigned)row, (unsigned)PXa) + b0 + rlo - mlo0;
+                uint32_t *ap = (uint32_t *)acc + 3 * node;
+                for (int m = rlo; m <= rhi; ++m) {
+                    atomicAdd(ap, fixed32(ax * w));
+                    atomicAdd(ap + 1, fixed32(ay * w));
+                    atomicAdd(ap + 2, fixed32(az * w));
+                    w *= rr;
+                    rr *= qx;
+                    ap += 3;
+                }
+            }
         }
     }
     __syncthreads();
+    // store: node x of a pencil row = index x - mlo plus its periodic images
+    // x + Nx - mlo (for x < mhi) and x - Nx - mlo (for x >= Nx + mlo)
     float *f = (float *)B.f;
     const float inv = 1.0f / scale;
-    const int64_t Nx = B.n[0], Ny = B.n[1];
-    const int64_t ng = Nx * Ny * B.n[2];
-    const int cnt = e0 * e1 * e2;
+    const int64_t ng = (int64_t)Nx * Ny * Nz;
+    const int cnt = Nx * e1 * e2;
     for (int i = tid; i < cnt; i += kScatterBlock) {
-        const int lx = i % e0;
-        const int ly = (i / e0) % e1;
-        const int lz = i / (e0 * e1);
-        const int64_t g = ((int64_t)(o2 + lz) * Ny + (o1 + ly)) * Nx + (o0 + lx);
-        const int a = 3 * (lz * PL + ly * PX + lx);
-        f[g] = (float)acc[a] * inv;
-        f[ng + g] = (float)acc[a + 1] * inv;
-        f[2 * ng + g] = (float)acc[a + 2] * inv;
+        const int x = i % Nx;
+        const int r = i / Nx;
+        const int ly = r % e1, lz = r / e1;
+        const int64_t g = ((int64_t)(o2 + lz) * Ny + (o1 + ly)) * Nx + x;
+        const int base = 3 * ((lz * T1 + ly) * PXa);
+        const int a = base + 3 * (x - mlo0);
+        int v0 = acc[a], v1 = acc[a + 1], v2 = acc[a + 2];
+        if (x < mhi0) {
+            const int a2 = a + 3 * Nx;
+            v0 += acc[a2];
+            v1 += acc[a2 + 1];
+            v2 += acc[a2 + 2];
+        }
+        if (x >= Nx + mlo0) {
+            const int a2 = a - 3 * Nx;
+            v0 += acc[a2];
+            v1 += acc[a2 + 1];
+            v2 += acc[a2 + 2];
+        }
+        f[g] = (float)v0 * inv;
+        f[ng + g] = (float)v1 * inv;
+        f[2 * ng + g] = (float)v2 * inv;
     }
 }
 
