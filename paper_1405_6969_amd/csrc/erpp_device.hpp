@@ -96,29 +96,29 @@ __device__ __forceinline__ bool inside32(int mx, float phx, float ryz, const Dev
 }
 
 // Contiguous range [lo, hi] of x offsets of row (my, mz) inside the sphere,
-// within [mlo, mhi]; lo > hi when the row is empty.  The ends are estimated from
-// the row's half-width s = sqrt(R^2 - ryz) / dx (raw v_sqrt, multiply by 1/dx).
-// Against the exact boundary (FP32 rounding plus the FP64 guard band) its error
-// in nodes is about (guard + ulp(R^2)) / (2 s dx^2) <= 5e-5 R^2 / (s dx^2), well
-// under one node for s >= 0.01; a row with smaller s holds at most the node
-// nearest phi, which the tests on either side of the estimate reach.
-// Each end is then settled by the exact decision (inside32) at the estimate and
-// one node outward; membership is monotone in |mx - phi| along a row.  The node
-// set is therefore the exact one, the same in every kernel that calls this.
+// within [mlo, mhi]; lo > hi when the row is empty.  Membership along a row is
+// monotone in |mx - phi|, so the row is [ceil(phi - s*), floor(phi + s*)] for
+// the exact half-width s* (in nodes).  Its estimate s = sqrt(R^2 - ryz) / dx
+// (raw v_sqrt, multiply by 1/dx) is within 0.01 node of s* -- (guard band +
+// FP32 rounding) / (2 s dx^2) -- whenever s >= 0.01.  Each end is then settled
+// by one exact decision (inside32 semantics) at the node nearest the estimated
+// end k: the end is k if k is inside, else the next node inward.  A row with
+// s < 0.01 can hold only the node nearest phi, which both ends then test.  The
+// node set is therefore the exact one, the same in every kernel that calls this.
 __device__ __forceinline__ void row_range(float phx, float ryz, const DevBox &B,
                                           const DevBox *Bp, int64_t slot, int pid, int my,
                                           int mz, int &lo, int &hi) {
     const float rem = fmaxf(B.R2f - ryz, 0.0f);
     const float s = __builtin_amdgcn_sqrtf(rem) * B.idxf0;
-    int l = (int)ceilf(phx - s), h = (int)floorf(phx + s);
-    const bool in_lm = inside32(l - 1, phx, ryz, B, Bp, slot, pid, my, mz);
-    const bool in_l = inside32(l, phx, ryz, B, Bp, slot, pid, my, mz);
-    const bool in_h = inside32(h, phx, ryz, B, Bp, slot, pid, my, mz);
-    const bool in_hp = inside32(h + 1, phx, ryz, B, Bp, slot, pid, my, mz);
-    l = in_lm ? l - 1 : (in_l ? l : l + 1);
-    h = in_hp ? h + 1 : (in_h ? h : h - 1);
-    lo = max(l, B.mlo[0]);
-    hi = min(h, B.mhi[0]);
+    const float kl = rintf(phx - s), kh = rintf(phx + s);
+    const float tl = (kl - phx) * B.dxf[0], th = (kh - phx) * B.dxf[0];
+    const float dl = fmaf(tl, tl, ryz), dh = fmaf(th, th, ryz);
+    const float below = B.R2f - B.guard, above = B.R2f + B.guard;
+    bool il = dl < below, ih = dh < below;
+    if (dl >= below && dl <= above) il = inside_exact(Bp, slot, pid, (int)kl, my, mz);
+    if (dh >= below && dh <= above) ih = inside_exact(Bp, slot, pid, (int)kh, my, mz);
+    lo = max((int)kl + (il ? 0 : 1), B.mlo[0]);
+    hi = min((int)kh - (ih ? 0 : 1), B.mhi[0]);
 }
 
 // ---------------------------------------------------------- self-disturbance --
