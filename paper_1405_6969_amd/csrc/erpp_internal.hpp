@@ -64,6 +64,7 @@ struct Scratch {
     int32_t *part = nullptr;     // [nchunk+1]      scan partials
     int32_t *rank = nullptr;     // [np_total]      rank of a particle inside its cell
     float4 *rec = nullptr;       // [2*np_total]    cell-sorted injection records
+    double4 *up = nullptr;       // [np_total]      carrier at the particles (FP64)
     // ERPP_F64_PLAIN
     double *pamp = nullptr;      // [4][np_total] -D/rho_f (3 components) and Z
     double *pphi = nullptr;      // [3][np_total] offsets inside the base cell
