@@ -148,7 +148,7 @@ static int32_t round4(int64_t v) { return (int32_t)((v + 3) & ~int64_t(3)); }
 // Pencils, block offsets and the scatter's LDS layout of every box for the
 // plan's tile.  Returns false when a pencil does not fit the LDS.
 bool fill_box_tiles(erpp_plan *p) {
-    int64_t cell = 0, bp = 0, bt = 0, br = 0;
+    int64_t cell = 0, key = 0, bp = 0, bt = 0, br = 0;
     int64_t lds_max = 0;
     for (auto &B : p->hbox) {
         int32_t ext[3];
@@ -163,6 +163,9 @@ bool fill_box_tiles(erpp_plan *p) {
         }
         B.cell_off = cell;
         cell += (int64_t)B.n[0] * B.n[1] * B.n[2];
+        B.nxb = (B.n[0] + (1 << kXBlockShift) - 1) >> kXBlockShift;
+        B.key_off = key;
+        key += (int64_t)B.nxb * B.n[1] * B.n[2];
         B.blk_p = bp;
         bp += (B.np + kBlock - 1) / kBlock;
         B.blk_t = bt;
@@ -179,6 +182,7 @@ bool fill_box_tiles(erpp_plan *p) {
         lds_max = std::max<int64_t>(lds_max, 4 * (B.lds_tab + round4(tabw)));
     }
     p->ncell_total = cell;
+    p->nkey_total = key;
     p->pblocks = bp;
     p->tblocks = bt;
     p->pblocks_rows = br;

@@ -17,6 +17,7 @@ constexpr int kBlock = 256;          // threads per block of particle kernels
 constexpr int kScatterBlock = 512;   // threads per block of the tiled scatter
 constexpr int kScatterWaves = kScatterBlock / 64;
 constexpr int kScanChunk = 4096;     // counters per block of the device-wide scan
+constexpr int kXBlockShift = 4;      // step binning: x-blocks of 16 cells per cell row
 
 // Everything a kernel needs to know about one box; lives in device memory as
 // an array indexed by box.  Plain old data.
@@ -30,7 +31,10 @@ struct DevBox {
     int32_t lds_tab;     // LDS word offset of the window's record-start table
     int64_t np;          // particles
     int64_t poff;        // first particle in the concatenated particle space
-    int64_t cell_off;    // first cell of this box in the concatenated cell-key space
+    int64_t cell_off;    // first cell of this box in the concatenated cell space (erpp_bin)
+    int64_t key_off;     // first key of this box in the step's (row, x-block) key space
+    int32_t nxb;         // x-blocks per cell row
+    int32_t pad0;
     int64_t blk_p;       // first block of this box in particle launches
     int64_t blk_t;       // first block of this box in tile launches
     int64_t blk_r;       // first block of this box in (particle, row) launches
@@ -88,6 +92,7 @@ struct erpp_plan {
     erpp::DevBox *dbox = nullptr;
     int64_t np_total = 0;
     int64_t ncell_total = 0;
+    int64_t nkey_total = 0;
     int64_t pblocks = 0;         // blocks of particle launches (box aligned)
     int64_t tblocks = 0;         // blocks of tile launches
     int64_t pblocks_rows = 0;    // plain scatter: blocks over (particle,row)

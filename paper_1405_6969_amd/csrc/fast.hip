@@ -1,8 +1,8 @@
 // fast.hip -- ERPP_F32_FAST path of the coupling step for gfx950.
 //
 // Per step n (all boxes of a plan in one launch per stage):
-//   k_bin_count   cell histogram of the delayed positions X^{n-M}; a particle's
-//                 atomic ticket is its rank inside its cell
+//   k_bin_count   histogram of the delayed positions X^{n-M} by cell row and
+//                 x-block; a particle's atomic ticket is its rank in its bin
 //   k_scan_*      device-wide exclusive scan of the histogram (and its reset)
 //   k_eval        per particle: FP64 cell/offset of X^{n-M}, FP32 Gaussian
 //                 normalisation over the 3-sigma sphere, record
@@ -28,6 +28,14 @@ __device__ __forceinline__ int64_t cell_key(const DevBox &B, int b0, int b1, int
     return ((int64_t)b2 * B.n[1] + b1) * B.n[0] + b0;
 }
 
+// Sort key of the step's binning: cell row (b1, b2), then x-block of
+// 2^kXBlockShift cells.  Records of a cell row stay contiguous (the scatter's
+// ranges) and in x-block order (the gather's locality), while the counters are
+// few enough to stay in L2.
+__device__ __forceinline__ int64_t step_key(const DevBox &B, int b0, int b1, int b2) {
+    return B.key_off + ((int64_t)b2 * B.n[1] + b1) * B.nxb + (b0 >> kXBlockShift);
+}
+
 __global__ void __launch_bounds__(kBlock) k_bin_count(const DevBox *__restrict__ Bs, int nbox,
                                                       const int64_t *__restrict__ stepp, int M,
                                                       int32_t *__restrict__ count,
@@ -44,7 +52,7 @@ __global__ void __launch_bounds__(kBlock) k_bin_count(const DevBox *__restrict__
     int b[3];
     double ph;
     for (int d = 0; d < 3; ++d) cell_of(X[d * np + p], B.L[d], B.dx[d], B.n[d], b[d], ph);
-    rank[B.poff + p] = atomicAdd(&count[B.cell_off + cell_key(B, b[0], b[1], b[2])], 1);
+    rank[B.poff + p] = atomicAdd(&count[step_key(B, b[0], b[1], b[2])], 1);
 }
 
 // ------------------------------------------------------------------ scan ----
@@ -158,8 +166,6 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
                                                  const int32_t *__restrict__ rank,
                                                  float4 *__restrict__ rec) {
     __shared__ float sP[kMaxOff + 1][kBlock];   // prefix sums of the x factors
-    __shared__ float sGy[kMaxOff][kBlock];
-    __shared__ float sTy[kMaxOff][kBlock];
     const int64_t n = *stepp;
     if (n < M) return;
     const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_p; });
@@ -176,8 +182,9 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
     for (int d = 0; d < 3; ++d) cell_of(X[d * np + p], B.L[d], B.dx[d], B.n[d], b[d], ph[d]);
     const float phx = (float)ph[0], phy = (float)ph[1], phz = (float)ph[2];
     const int mlo0 = B.mlo[0], mhi0 = B.mhi[0];
-    const int mlo1 = B.mlo[1], mhi1 = B.mhi[1];
-    // x factors and their prefix sums, y factors
+    const int mlo1 = B.mlo[1], ny = B.mhi[1] - B.mlo[1] + 1;
+    // prefix sums of the x factors (indexed by row ends: LDS); y factors and
+    // offsets in registers (row loop unrolled over the maximum stencil width)
     sP[0][tid] = 0.0f;
     {
         float acc = 0.0f;
@@ -186,9 +193,11 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
             sP[m - mlo0 + 1][tid] = acc;
         }
     }
-    for (int m = mlo1; m <= mhi1; ++m) {
-        sGy[m - mlo1][tid] = g1(m, phy, B.dxf[1], B.cexp);
-        sTy[m - mlo1][tid] = d1(m, phy, B.dxf[1]);
+    float gy[kMaxOff], ty[kMaxOff];
+#pragma unroll
+    for (int j = 0; j < kMaxOff; ++j) {
+        gy[j] = (j < ny) ? g1(mlo1 + j, phy, B.dxf[1], B.cexp) : 0.0f;
+        ty[j] = (j < ny) ? d1(mlo1 + j, phy, B.dxf[1]) : 0.0f;
     }
     const float cut = B.R2f + B.guard;
     const int pid = (int)p;
@@ -198,23 +207,25 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
         const float tz2 = tz * tz;
         if (tz2 > cut) continue;
         const float gz = g1(mz, phz, B.dxf[2], B.cexp);
-        for (int my = mlo1; my <= mhi1; ++my) {
-            const float ty = sTy[my - mlo1][tid];
-            const float ryz = fmaf(ty, ty, tz2);
-            if (ryz > cut) continue;
-            int lo, hi;
-            row_range(phx, ryz, B, &B, slot, pid, my, mz, lo, hi);
-            if (lo > hi) continue;
-            const float gyz = sGy[my - mlo1][tid] * gz;
-            const float rs = sP[hi - mlo0 + 1][tid] - sP[lo - mlo0][tid];
-            Z = fmaf(gyz, rs, Z);
+        float Zp = 0.0f;
+#pragma unroll
+        for (int j = 0; j < kMaxOff; ++j) {
+            if (j < ny) {
+                const float ryz = fmaf(ty[j], ty[j], tz2);
+                if (ryz <= cut) {
+                    int lo, hi;
+                    row_range(phx, ryz, B, &B, slot, pid, mlo1 + j, mz, lo, hi);
+                    if (lo <= hi) Zp = fmaf(gy[j], sP[hi - mlo0 + 1][tid] - sP[lo - mlo0][tid], Zp);
+                }
+            }
         }
+        Z = fmaf(gz, Zp, Z);
     }
     const float Zv = Z * (float)B.dV;
     const float inv = -B.rhof_inv / Zv;
     const float ax = Dd[p] * inv, ay = Dd[np + p] * inv, az = Dd[2 * np + p] * inv;
     const int64_t slotr =
-        (int64_t)start[B.cell_off + cell_key(B, b[0], b[1], b[2])] + rank[B.poff + p];
+        (int64_t)start[step_key(B, b[0], b[1], b[2])] + rank[B.poff + p];
     const uint32_t ijk = (uint32_t)b[0] | ((uint32_t)b[1] << 11) | ((uint32_t)b[2] << 22);
     rec[2 * slotr] = make_float4(phx, phy, phz, __uint_as_float(ijk));
     rec[2 * slotr + 1] = make_float4(ax, ay, az, __int_as_float((int)p));
@@ -302,9 +313,9 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
         for (int k = tid; k < WZ * TW; k += kScatterBlock) {
             const int wz = k / TW, j = k - wz * TW;
             const int b2 = wrap_index(o2 - mhi2 + wz, Nz);
-            const int64_t plane = B.cell_off + (int64_t)b2 * Ny * Nx;
+            const int64_t plane = B.key_off + (int64_t)b2 * Ny * B.nxb;
             const int b1 = (j <= WY) ? wrap_index(o1 - mhi1 + j, Ny) : Ny;
-            tab[k] = start[plane + (int64_t)b1 * Nx];
+            tab[k] = start[plane + (int64_t)b1 * B.nxb];
         }
         // row classes that some particle can reach: nearest approach of the row to
         // a base-cell offset in [0, 1)^2 within the cut-off
@@ -620,7 +631,7 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                                    P->dbox, P->nbox, P->s.step, P->M, P->s.count, P->s.rank);
             break;
         case 1:
-            return scan_counts(P->s.count, P->ncell_total, P->s.start, P->s.part, st);
+            return scan_counts(P->s.count, P->nkey_total, P->s.start, P->s.part, st);
         case 2:
             if (P->np_total > 0)
                 hipLaunchKernelGGL(k_eval, dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
