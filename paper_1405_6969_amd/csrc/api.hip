@@ -62,6 +62,8 @@ void free_scratch(erpp_plan *p) {
     (void)hipFree(s.rank);
     (void)hipFree(s.rec);
     (void)hipFree(s.up);
+    (void)hipFree(s.xs);
+    (void)hipFree(s.sl);
     (void)hipFree(s.part);
     (void)hipFree(s.pamp);
     (void)hipFree(s.pphi);
@@ -312,7 +314,9 @@ erpp_status erpp_plan_create(erpp_plan **out, const erpp_box *boxes, int32_t nbo
               alloc(&p->s.rank, (size_t)np_total) == hipSuccess;
     if (ok && prec == ERPP_F32_FAST)
         ok = alloc(&p->s.rec, 2 * (size_t)np_total) == hipSuccess &&
-             alloc(&p->s.up, (size_t)np_total) == hipSuccess;
+             alloc(&p->s.up, (size_t)np_total) == hipSuccess &&
+             alloc(&p->s.xs, (size_t)np_total) == hipSuccess &&
+             alloc(&p->s.sl, (size_t)np_total) == hipSuccess;
     if (ok && prec == ERPP_F64_PLAIN)
         ok = alloc(&p->s.pamp, 4 * (size_t)np_total) == hipSuccess &&
              alloc(&p->s.pphi, 3 * (size_t)np_total) == hipSuccess &&

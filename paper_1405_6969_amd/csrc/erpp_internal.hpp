@@ -68,7 +68,9 @@ struct Scratch {
     int32_t *part = nullptr;     // [nchunk+1]      scan partials
     int32_t *rank = nullptr;     // [np_total]      rank of a particle inside its cell
     float4 *rec = nullptr;       // [2*np_total]    cell-sorted injection records
-    double4 *up = nullptr;       // [np_total]      carrier at the particles (FP64)
+    double4 *xs = nullptr;       // [np_total]      x^n in record order
+    double4 *up = nullptr;       // [np_total]      carrier at x^n in record order (FP64)
+    int32_t *sl = nullptr;       // [np_total]      record slot of each particle
     // ERPP_F64_PLAIN
     double *pamp = nullptr;      // [4][np_total] -D/rho_f (3 components) and Z
     double *pphi = nullptr;      // [3][np_total] offsets inside the base cell

@@ -164,7 +164,9 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
                                                  const int64_t *__restrict__ stepp, int M,
                                                  const int32_t *__restrict__ start,
                                                  const int32_t *__restrict__ rank,
-                                                 float4 *__restrict__ rec) {
+                                                 float4 *__restrict__ rec,
+                                                 double4 *__restrict__ xs,
+                                                 int32_t *__restrict__ sl) {
     __shared__ float sP[kMaxOff + 1][kBlock];   // prefix sums of the x factors
     const int64_t n = *stepp;
     if (n < M) return;
@@ -229,6 +231,9 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
     const uint32_t ijk = (uint32_t)b[0] | ((uint32_t)b[1] << 11) | ((uint32_t)b[2] << 22);
     rec[2 * slotr] = make_float4(phx, phy, phz, __uint_as_float(ijk));
     rec[2 * slotr + 1] = make_float4(ax, ay, az, __int_as_float((int)p));
+    // the current position x^n, in record order for the carrier gather
+    xs[slotr] = make_double4(B.x[p], B.x[np + p], B.x[2 * np + p], 0.0);
+    sl[B.poff + p] = (int32_t)slotr;
 }
 
 // --------------------------------------------------------------- scatter ----
@@ -489,14 +494,14 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
 }
 
 // Carrier at the particles, visited in the cell order of their delayed
-// positions (records of level n - M): particles move far less than a cell in M
-// steps, so neighbouring threads read neighbouring carrier nodes and the field
-// streams through L2 about once, instead of eight scattered rows per particle.
-// The FP64 trilinear value (plus the mean shear) is stored per particle for the
-// update kernel, which runs in particle order.
+// positions (record order of level n - M): particles move far less than a cell
+// in M steps, so neighbouring threads read neighbouring carrier nodes and the
+// field streams through L2 about once, instead of eight scattered rows per
+// particle.  x^n arrives in record order from the evaluation kernel; the FP64
+// trilinear value (plus the mean shear) is stored in record order too.
 __global__ void __launch_bounds__(kBlock) k_gather_sorted(const DevBox *__restrict__ Bs, int nbox,
                                                           const int64_t *__restrict__ stepp,
-                                                          int M, const float4 *__restrict__ rec,
+                                                          int M, const double4 *__restrict__ xs,
                                                           double4 *__restrict__ up) {
     const int64_t n = *stepp;
     if (n < M) return;
@@ -506,18 +511,18 @@ __global__ void __launch_bounds__(kBlock) k_gather_sorted(const DevBox *__restri
     if (r >= B.np) return;
     // the records of a box are [poff, poff + np): its cells follow the cells of
     // the boxes before it in the scanned key space
-    const int64_t p = __float_as_int(rec[2 * (B.poff + r) + 1].w);
-    const int64_t np = B.np;
-    double xp[3] = {B.x[p], B.x[np + p], B.x[2 * np + p]};
+    const double4 x4 = xs[B.poff + r];
+    double xp[3] = {x4.x, x4.y, x4.z};
     double u[3];
     trilinear<float>(B, (const float *)B.u, xp, u);
-    up[B.poff + p] = make_double4(u[0], u[1], u[2], 0.0);
+    up[B.poff + r] = make_double4(u[0], u[1], u[2], 0.0);
 }
 
 __global__ void __launch_bounds__(kBlock) k_update(const DevBox *__restrict__ Bs, int nbox,
                                                    const int64_t *__restrict__ stepp, int M,
                                                    double dt, int selfc,
-                                                   const double4 *__restrict__ upc) {
+                                                   const double4 *__restrict__ upc,
+                                                   const int32_t *__restrict__ sl) {
     const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_p; });
     const DevBox &B = Bs[bi];
     const int64_t p = (int64_t)(blockIdx.x - B.blk_p) * kBlock + threadIdx.x;
@@ -527,8 +532,8 @@ __global__ void __launch_bounds__(kBlock) k_update(const DevBox *__restrict__ Bs
     double xp[3] = {B.x[p], B.x[np + p], B.x[2 * np + p]};
     double up[3];
     if (n >= M) {
-        // gathered in cell order by k_gather_sorted
-        const double4 g = upc[B.poff + p];
+        // gathered in record order by k_gather_sorted
+        const double4 g = upc[sl[B.poff + p]];
         up[0] = g.x;
         up[1] = g.y;
         up[2] = g.z;
@@ -636,7 +641,7 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
             if (P->np_total > 0)
                 hipLaunchKernelGGL(k_eval, dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step, P->M, P->s.start, P->s.rank,
-                                   P->s.rec);
+                                   P->s.rec, P->s.xs, P->s.sl);
             break;
         case 3:
             hipLaunchKernelGGL(k_scatter, dim3((unsigned)P->tblocks), dim3(kScatterBlock),
@@ -646,10 +651,10 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
         case 4:
             if (P->np_total > 0) {
                 hipLaunchKernelGGL(k_gather_sorted, dim3((unsigned)P->pblocks), dim3(kBlock), 0,
-                                   st, P->dbox, P->nbox, P->s.step, P->M, P->s.rec, P->s.up);
+                                   st, P->dbox, P->nbox, P->s.step, P->M, P->s.xs, P->s.up);
                 hipLaunchKernelGGL(k_update, dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step, P->M, P->dt, P->self_correction,
-                                   P->s.up);
+                                   P->s.up, P->s.sl);
             }
             break;
         default:
