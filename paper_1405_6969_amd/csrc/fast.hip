@@ -251,7 +251,6 @@ __device__ __forceinline__ uint32_t fixed32(float v) {
     return (uint32_t)r;
 }
 
-constexpr int kMaxRanges = 2 * kMaxTileZ;   // record ranges of one row class (two per plane)
 
 // One workgroup per pencil of nodes: the whole x extent of the box times
 // T1 x T2 nodes in (y, z).  Owner computes: every node of the pencil is written
@@ -279,6 +278,9 @@ constexpr int kMaxRanges = 2 * kMaxTileZ;   // record ranges of one row class (t
 // (the raw Gaussian is <= 1), and added with ds_add_u32 (the FP32 LDS atomic
 // runs ~40x slower on gfx950).  Integer additions commute, so the forcing does
 // not depend on the order of the adds.
+// TZ: the plan's pencil depth rounded up to a power of two (>= every box's T2);
+// a row class has at most 2 TZ record ranges.
+template <int TZ>
 __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restrict__ Bs,
                                                            int nbox,
                                                            const int64_t *__restrict__ stepp,
@@ -397,6 +399,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
             // item q of range k is record q + off_k (pre_k <= q < pre_k + len_k)
             const int pre = incl - len;
             const int off = gb - pre;
+            constexpr int kMaxRanges = 2 * TZ;
             int pre_k[kMaxRanges], off_k[kMaxRanges];
 #pragma unroll
             for (int k = 0; k < kMaxRanges; ++k) {
@@ -624,8 +627,13 @@ hipError_t scan_counts(int32_t *count, int64_t n, int32_t *start, int32_t *part,
 }
 
 hipError_t fast_prepare_lds(size_t bytes) {
-    return hipFuncSetAttribute((const void *)k_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)bytes);
+    const void *fns[] = {(const void *)k_scatter<1>, (const void *)k_scatter<2>,
+                         (const void *)k_scatter<4>, (const void *)k_scatter<8>};
+    for (const void *fn : fns) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
@@ -644,9 +652,14 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                                    P->s.rec, P->s.xs, P->s.sl);
             break;
         case 3:
-            hipLaunchKernelGGL(k_scatter, dim3((unsigned)P->tblocks), dim3(kScatterBlock),
-                               P->lds_bytes, st, P->dbox, P->nbox, P->s.step, P->M, P->s.start,
-                               P->s.rec);
+            {
+                const int tz = P->tile[2];
+                auto fn = tz <= 1 ? k_scatter<1> : tz <= 2 ? k_scatter<2>
+                                                 : tz <= 4 ? k_scatter<4> : k_scatter<8>;
+                hipLaunchKernelGGL(fn, dim3((unsigned)P->tblocks), dim3(kScatterBlock),
+                                   P->lds_bytes, st, P->dbox, P->nbox, P->s.step, P->M,
+                                   P->s.start, P->s.rec);
+            }
             break;
         case 4:
             if (P->np_total > 0) {
