@@ -448,18 +448,24 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
                 const float t0 = ((float)rlo - qa.x) * hx;
                 float w = __builtin_amdgcn_exp2f(-fmaf(t0, t0, ryz) * c);
                 float rr = __builtin_amdgcn_exp2f(-c * hx * fmaf(2.0f, t0, hx));
-                const float ax = qb.x * scale, ay = qb.y * scale, az = qb.z * scale;
+                // contributions a_c w of the row's first node, advanced along the row
+                // by the weight ratio rr (itself advanced by qx)
+                const float sw = scale * w;
+                float cx = qb.x * sw, cy = qb.y * sw, cz = qb.z * sw;
                 const int row = (int)__umul24((unsigned)z, (unsigned)T1) + y;
                 const int node = (int)__umul24((unsigned)row, (unsigned)PXa) + b0 + rlo - mlo0;
                 uint32_t *ap = (uint32_t *)acc + 3 * node;
-                for (int m = rlo; m <= rhi; ++m) {
-                    atomicAdd(ap, fixed32(ax * w));
-                    atomicAdd(ap + 1, fixed32(ay * w));
-                    atomicAdd(ap + 2, fixed32(az * w));
-                    w *= rr;
+                uint32_t *const ae = ap + 3 * (rhi - rlo + 1);
+                do {
+                    atomicAdd(ap, fixed32(cx));
+                    atomicAdd(ap + 1, fixed32(cy));
+                    atomicAdd(ap + 2, fixed32(cz));
+                    cx *= rr;
+                    cy *= rr;
+                    cz *= rr;
                     rr *= qx;
                     ap += 3;
-                }
+                } while (ap != ae);
             }
         }
     }
