@@ -65,6 +65,7 @@ void free_scratch(erpp_plan *p) {
     (void)hipFree(s.xs);
     (void)hipFree(s.sl);
     (void)hipFree(s.part);
+    (void)hipFree(s.ticket);
     (void)hipFree(s.pamp);
     (void)hipFree(s.pphi);
     (void)hipFree(s.pbase);
@@ -99,8 +100,9 @@ erpp_status alloc_bins(erpp_plan *p) {
     const size_t nc = (size_t)std::max<int64_t>(p->ncell_total, 1);
     const size_t nchunk = (nc + erpp::kScanChunk - 1) / erpp::kScanChunk;
     if (alloc(&p->s.count, nc) != hipSuccess || alloc(&p->s.start, nc + 1) != hipSuccess ||
-        alloc(&p->s.part, nchunk + 1) != hipSuccess)
+        alloc(&p->s.part, nchunk + 1) != hipSuccess || alloc(&p->s.ticket, 1) != hipSuccess)
         return fail(ERPP_ENOMEM, "cell arrays (%lld cells)", (long long)p->ncell_total);
+    HIP_OR_RETURN(hipMemset(p->s.ticket, 0, sizeof(int32_t)));
     HIP_OR_RETURN(hipMemset(p->s.count, 0, sizeof(int32_t) * nc));
     HIP_OR_RETURN(hipMemset(p->s.start, 0, sizeof(int32_t) * (nc + 1)));
     return ERPP_OK;
@@ -310,7 +312,7 @@ erpp_status erpp_plan_create(erpp_plan **out, const erpp_box *boxes, int32_t nbo
             return fail(ERPP_EUNSUPPORTED, "stencil too wide for the scatter's LDS tile");
         }
     }
-    bool ok = alloc(&p->dbox, (size_t)nbox) == hipSuccess && alloc(&p->s.step, 1) == hipSuccess &&
+    bool ok = alloc(&p->dbox, (size_t)nbox) == hipSuccess && alloc(&p->s.step, 2) == hipSuccess &&
               alloc(&p->s.rank, (size_t)np_total) == hipSuccess;
     if (ok && prec == ERPP_F32_FAST)
         ok = alloc(&p->s.rec, 2 * (size_t)np_total) == hipSuccess &&
@@ -329,7 +331,7 @@ erpp_status erpp_plan_create(erpp_plan **out, const erpp_box *boxes, int32_t nbo
     }
     erpp_status s = alloc_bins(p);
     if (s == ERPP_OK) s = upload_boxes(p);
-    if (s == ERPP_OK && hipMemset(p->s.step, 0, sizeof(int64_t)) != hipSuccess)
+    if (s == ERPP_OK && hipMemset(p->s.step, 0, 2 * sizeof(int64_t)) != hipSuccess)
         s = fail(ERPP_EHIP, "hipMemset of the step counter");
     if (s != ERPP_OK) {
         free_scratch(p);
@@ -433,7 +435,8 @@ erpp_status erpp_run(erpp_plan *p, int64_t step0, int64_t nsteps, int32_t use_gr
             return hip_fail(e, "hipStreamBeginCapture");
         }
         erpp_status s = run_stages(p, cap, true);
-        hipError_t e2 = erpp::advance_step(p, cap);
+        // the fast path's scan advances the step index itself
+        hipError_t e2 = p->prec == ERPP_F64_PLAIN ? erpp::advance_step(p, cap) : hipSuccess;
         hipGraph_t g = nullptr;
         hipError_t e3 = hipStreamEndCapture(cap, &g);
         (void)hipStreamDestroy(cap);
@@ -465,7 +468,7 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
     hipStream_t st = as_stream(stream);
     // geometry key
     std::ostringstream key;
-    key << "v3 M" << p->M << " nbox" << p->nbox;
+    key << "v4 M" << p->M << " nbox" << p->nbox;
     for (const auto &B : p->hbox)
         key << " " << B.n[0] << "x" << B.n[1] << "x" << B.n[2] << ":" << B.np << ":" << B.mlo[0]
             << "," << B.mhi[0];
@@ -482,9 +485,9 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
                 return erpp_plan_set_tile(p, t);
         }
     }
-    static const int32_t cand[][3] = {{0, 4, 4}, {0, 2, 2}, {0, 4, 2}, {0, 2, 4},
-                                      {0, 8, 2}, {0, 8, 4}, {0, 4, 8}, {0, 1, 2},
-                                      {0, 2, 1}, {0, 1, 1}, {0, 8, 8}, {0, 16, 2}};
+    static const int32_t cand[][3] = {{0, 16, 1}, {0, 8, 2}, {0, 8, 1}, {0, 4, 4},
+                                      {0, 4, 2}, {0, 32, 1}, {0, 16, 2}, {0, 2, 2},
+                                      {0, 4, 1}, {0, 2, 4}, {0, 1, 2}, {0, 8, 4}};
     const int ncand = (int)(sizeof cand / sizeof cand[0]);
     int32_t best[3] = {p->tile[0], p->tile[1], p->tile[2]};
     float best_ms = 1e30f;
@@ -502,7 +505,7 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
         status = erpp_scatter(p, n, stream);   // warm-up
         if (status != ERPP_OK) break;
         (void)hipEventRecord(a, st);
-        const int reps = 3;
+        const int reps = 5;
         for (int r = 0; r < reps && status == ERPP_OK; ++r) status = erpp_scatter(p, n, stream);
         (void)hipEventRecord(b, st);
         if (hipEventSynchronize(b) != hipSuccess) {

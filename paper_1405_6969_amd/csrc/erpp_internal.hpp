@@ -66,6 +66,7 @@ struct Scratch {
     int32_t *count = nullptr;    // [ncell_total]   per-step cell histogram (kept zero at rest)
     int32_t *start = nullptr;    // [ncell_total+1] exclusive scan of count
     int32_t *part = nullptr;     // [nchunk+1]      scan partials
+    int32_t *ticket = nullptr;   // [1]             scan: workgroups done (zero at rest)
     int32_t *rank = nullptr;     // [np_total]      rank of a particle inside its cell
     float4 *rec = nullptr;       // [2*np_total]    cell-sorted injection records
     double4 *xs = nullptr;       // [np_total]      x^n in record order
@@ -76,7 +77,9 @@ struct Scratch {
     double *pphi = nullptr;      // [3][np_total] offsets inside the base cell
     int32_t *pbase = nullptr;    // [3][np_total] base cell
     // both
-    int64_t *step = nullptr;     // device copy of the step index
+    int64_t *step = nullptr;     // [2] step index: [0] next step to run (set by the host,
+                                 // advanced by the scan of the fast path or by a kernel
+                                 // of its own in the plain path), [1] the step in progress
 };
 
 }  // namespace erpp
@@ -119,8 +122,9 @@ hipError_t plain_update_stage(erpp_plan *p, hipStream_t st);
 hipError_t set_step(erpp_plan *p, int64_t n, hipStream_t st);
 hipError_t advance_step(erpp_plan *p, hipStream_t st);
 bool fill_box_tiles(erpp_plan *p);          // tiles, blocks, LDS layout; false if it does not fit
-hipError_t scan_counts(int32_t *count, int64_t n, int32_t *start, int32_t *part,
-                       hipStream_t st);     // start = exclusive scan of count; count = 0
+// start = exclusive scan of count, count = 0; with stepp, also step[1] = step[0]++
+hipError_t scan_counts(int32_t *count, int64_t n, int32_t *start, int32_t *part, int32_t *ticket,
+                       int64_t *stepp, hipStream_t st);
 hipError_t fast_prepare_lds(size_t bytes);         // opt the scatter into > 64 KB LDS
 constexpr size_t kMaxScatterLds = 150 * 1024;
 constexpr size_t kScatterLdsTarget = 74 * 1024;   // two workgroups per CU (with static LDS)

@@ -3,7 +3,8 @@
 // Per step n (all boxes of a plan in one launch per stage):
 //   k_bin_count   histogram of the delayed positions X^{n-M} by cell row and
 //                 x-block; a particle's atomic ticket is its rank in its bin
-//   k_scan_*      device-wide exclusive scan of the histogram (and its reset)
+//   k_scan_*      device-wide exclusive scan of the histogram (and its reset);
+//                 publishes the step index for the kernels after it
 //   k_eval        per particle: FP64 cell/offset of X^{n-M}, FP32 Gaussian
 //                 normalisation over the 3-sigma sphere, record
 //                 {offsets, amplitude} written at its cell-sorted slot
@@ -56,9 +57,9 @@ __global__ void __launch_bounds__(kBlock) k_bin_count(const DevBox *__restrict__
 }
 
 // ------------------------------------------------------------------ scan ----
-// start[0..n] = exclusive scan of count[0..n), count reset to zero.  Three
-// launches: per-chunk sums, scan of the chunk sums (one workgroup), per-chunk
-// scan with its offset.  Chunks of kScanChunk counters, 256 threads x 16.
+// start[0..n] = exclusive scan of count[0..n), count reset to zero.  Two
+// launches: per-chunk sums (the last workgroup also scans them), then the
+// per-chunk scan with its offset.  Chunks of kScanChunk counters, 256 x 16.
 
 __device__ __forceinline__ int wave_incl_scan(int x) {
     const int lane = threadIdx.x & 63;
@@ -87,9 +88,16 @@ __device__ __forceinline__ int block_excl_scan(int v, int *sw, int nw, int *tota
     return pre + x - v;
 }
 
+// Per-chunk sums; the last workgroup to finish (device-scope ticket) scans them
+// in place (part[nchunk] = total), resets the ticket, and -- for the step's own
+// binning -- publishes the step index: stepp[1] = stepp[0] (read by the kernels
+// after the scan), stepp[0] += 1 (the next step).
 __global__ void __launch_bounds__(256) k_scan_reduce(const int32_t *__restrict__ count,
-                                                     int64_t n, int32_t *__restrict__ part) {
+                                                     int64_t n, int32_t *__restrict__ part,
+                                                     int64_t nchunk, int32_t *__restrict__ ticket,
+                                                     int64_t *__restrict__ stepp) {
     __shared__ int sw[4];
+    __shared__ int s_last;
     const int64_t base = (int64_t)blockIdx.x * kScanChunk;
     int s = 0;
     for (int j = 0; j < kScanChunk / 256; ++j) {
@@ -99,25 +107,35 @@ __global__ void __launch_bounds__(256) k_scan_reduce(const int32_t *__restrict__
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) part[blockIdx.x] = sw[0] + sw[1] + sw[2] + sw[3];
-}
-
-// part[0..nchunk) -> exclusive scan in place, part[nchunk] = total.
-__global__ void __launch_bounds__(1024) k_scan_top(int32_t *__restrict__ part, int64_t nchunk) {
-    __shared__ int sw[16];
-    const int64_t per = (nchunk + 1023) / 1024;
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = sw[0] + sw[1] + sw[2] + sw[3];
+        __threadfence();
+        s_last = atomicAdd(ticket, 1) == (int)(nchunk - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    const int64_t per = (nchunk + 255) / 256;
     const int64_t a = threadIdx.x * per;
     const int64_t e = (a + per < nchunk) ? a + per : nchunk;
-    int s = 0;
-    for (int64_t i = a; i < e; ++i) s += part[i];
+    int t = 0;
+    for (int64_t i = a; i < e; ++i) t += part[i];
     int total;
-    int run = block_excl_scan(s, sw, 16, &total);
+    int run = block_excl_scan(t, sw, 4, &total);
     for (int64_t i = a; i < e; ++i) {
         const int c = part[i];
         part[i] = run;
         run += c;
     }
-    if (threadIdx.x == 0) part[nchunk] = total;
+    if (threadIdx.x == 0) {
+        part[nchunk] = total;
+        *ticket = 0;
+        if (stepp) {
+            const int64_t cur = stepp[0];
+            stepp[1] = cur;
+            stepp[0] = cur + 1;
+        }
+    }
 }
 
 __global__ void __launch_bounds__(256) k_scan_down(int32_t *__restrict__ count, int64_t n,
@@ -622,11 +640,12 @@ __global__ void __launch_bounds__(kBlock) k_bin_pos_place(const DevBox *__restri
 
 }  // namespace
 
-hipError_t scan_counts(int32_t *count, int64_t n, int32_t *start, int32_t *part, hipStream_t st) {
+hipError_t scan_counts(int32_t *count, int64_t n, int32_t *start, int32_t *part, int32_t *ticket,
+                       int64_t *stepp, hipStream_t st) {
     const int64_t nchunk = (n + kScanChunk - 1) / kScanChunk;
     if (nchunk == 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nchunk), dim3(256), 0, st, count, n, part);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, part, nchunk);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nchunk), dim3(256), 0, st, count, n, part,
+                       nchunk, ticket, stepp);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nchunk), dim3(256), 0, st, count, n, part,
                        nchunk, start);
     return hipGetLastError();
@@ -650,11 +669,12 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                                    P->dbox, P->nbox, P->s.step, P->M, P->s.count, P->s.rank);
             break;
         case 1:
-            return scan_counts(P->s.count, P->nkey_total, P->s.start, P->s.part, st);
+            return scan_counts(P->s.count, P->nkey_total, P->s.start, P->s.part, P->s.ticket,
+                               P->s.step, st);
         case 2:
             if (P->np_total > 0)
                 hipLaunchKernelGGL(k_eval, dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
-                                   P->dbox, P->nbox, P->s.step, P->M, P->s.start, P->s.rank,
+                                   P->dbox, P->nbox, P->s.step + 1, P->M, P->s.start, P->s.rank,
                                    P->s.rec, P->s.xs, P->s.sl);
             break;
         case 3:
@@ -663,16 +683,16 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                 auto fn = tz <= 1 ? k_scatter<1> : tz <= 2 ? k_scatter<2>
                                                  : tz <= 4 ? k_scatter<4> : k_scatter<8>;
                 hipLaunchKernelGGL(fn, dim3((unsigned)P->tblocks), dim3(kScatterBlock),
-                                   P->lds_bytes, st, P->dbox, P->nbox, P->s.step, P->M,
+                                   P->lds_bytes, st, P->dbox, P->nbox, P->s.step + 1, P->M,
                                    P->s.start, P->s.rec);
             }
             break;
         case 4:
             if (P->np_total > 0) {
                 hipLaunchKernelGGL(k_gather_sorted, dim3((unsigned)P->pblocks), dim3(kBlock), 0,
-                                   st, P->dbox, P->nbox, P->s.step, P->M, P->s.xs, P->s.up);
+                                   st, P->dbox, P->nbox, P->s.step + 1, P->M, P->s.xs, P->s.up);
                 hipLaunchKernelGGL(k_update, dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
-                                   P->dbox, P->nbox, P->s.step, P->M, P->dt, P->self_correction,
+                                   P->dbox, P->nbox, P->s.step + 1, P->M, P->dt, P->self_correction,
                                    P->s.up, P->s.sl);
             }
             break;
@@ -710,7 +730,7 @@ hipError_t fast_bin_positions(erpp_plan *P, int ibox, const double *pos, int32_t
                            key, P->s.count, P->s.rank);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = scan_counts(P->s.count + H.cell_off, nc, bin_start, P->s.part, st);
+    e = scan_counts(P->s.count + H.cell_off, nc, bin_start, P->s.part, P->s.ticket, nullptr, st);
     if (e != hipSuccess) return e;
     if (H.np > 0)
         hipLaunchKernelGGL(k_bin_pos_place, dim3(blocks), dim3(kBlock), 0, st, P->dbox, ibox, key,
