@@ -403,13 +403,19 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
         for (int ci = wv; ci < ncls; ci += kScatterWaves) {
             const int cl = s_cls[ci];
             const int dy = mlo1 + cl % ny, dz = mlo2 + cl / ny;
-            // lane k < 2 e2: part (k & 1) of the records of plane k >> 1
-            int len = 0, gb = 0;
+            // lane k < 2 e2: part (k & 1) of the records of plane k >> 1.  Part 0
+            // holds cell rows b1 in [b1a, ...), part 1 (rows wrapped past Ny)
+            // b1 in [0, ...), with b1a = (o1 - dy) mod Ny: the pencil row of a
+            // record is lz T1 + b1 - b1a (+ Ny in part 1), so its LDS node index is
+            // b1 PXa + b0 + m + rowoff with rowoff uniform over the range
+            const int b1a = wrap_index(o1 - dy, Ny);
+            int len = 0, gb = 0, rowoff = 0;
             if (lane < nr) {
                 int g0, g1, h0, h1;
                 ranges((lane >> 1) + mhi2 - dz, mhi1 - dy, e1, g0, g1, h0, h1);
                 gb = (lane & 1) ? h0 : g0;
                 len = (lane & 1) ? h1 - h0 : g1 - g0;
+                rowoff = ((lane >> 1) * T1 - b1a + ((lane & 1) ? Ny : 0)) * PXa - mlo0;
             }
             const int incl = wave_incl_scan(len);
             const int total = __shfl(incl, 63, 64);
@@ -418,43 +424,44 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
             const int pre = incl - len;
             const int off = gb - pre;
             constexpr int kMaxRanges = 2 * TZ;
-            int pre_k[kMaxRanges], off_k[kMaxRanges];
+            int pre_k[kMaxRanges], off_k[kMaxRanges], row_k[kMaxRanges];
 #pragma unroll
             for (int k = 0; k < kMaxRanges; ++k) {
                 pre_k[k] = __builtin_amdgcn_readlane(pre, k);
                 off_k[k] = __builtin_amdgcn_readlane(off, k);
+                row_k[k] = __builtin_amdgcn_readlane(rowoff, k);
             }
-            auto record_of = [&](int q) -> int {
+            auto record_of = [&](int q, int &ro) -> int {
                 int o = off_k[0];
+                ro = row_k[0];
 #pragma unroll
                 for (int k = 1; k < kMaxRanges; ++k)
-                    if (k < nr) o = (q >= pre_k[k]) ? off_k[k] : o;
+                    if (k < nr && q >= pre_k[k]) {
+                        o = off_k[k];
+                        ro = row_k[k];
+                    }
                 return q + o;
             };
-            int q = lane;
+            int q = lane, nro = 0;
             float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na;
             if (q < total) {
-                const int g = record_of(q);
+                const int g = record_of(q, nro);
                 na = rec[2 * (int64_t)g];
                 nb = rec[2 * (int64_t)g + 1];
             }
             while (q < total) {
                 const float4 qa = na, qb = nb;
+                const int ro = nro;
                 const int qn = q + 64;
                 if (qn < total) {
-                    const int g = record_of(qn);
+                    const int g = record_of(qn, nro);
                     na = rec[2 * (int64_t)g];
                     nb = rec[2 * (int64_t)g + 1];
                 }
                 q = qn;
                 const uint32_t ijk = __float_as_uint(qa.w);
                 const int b0 = (int)(ijk & 2047u);
-                int y = (int)((ijk >> 11) & 2047u) + dy - o1;
-                int z = (int)(ijk >> 22) + dz - o2;
-                y += (y < 0) ? Ny : 0;
-                y -= (y >= Ny) ? Ny : 0;
-                z += (z < 0) ? Nz : 0;
-                z -= (z >= Nz) ? Nz : 0;
+                const int b1 = (int)((ijk >> 11) & 2047u);
                 const float tyv = d1(dy, qa.y, hy);
                 const float tzv = d1(dz, qa.z, hz);
                 const float ryz = fmaf(tyv, tyv, tzv * tzv);
@@ -470,8 +477,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
                 // by the weight ratio rr (itself advanced by qx)
                 const float sw = scale * w;
                 float cx = qb.x * sw, cy = qb.y * sw, cz = qb.z * sw;
-                const int row = (int)__umul24((unsigned)z, (unsigned)T1) + y;
-                const int node = (int)__umul24((unsigned)row, (unsigned)PXa) + b0 + rlo - mlo0;
+                const int node = (int)__umul24((unsigned)b1, (unsigned)PXa) + b0 + rlo + ro;
                 uint32_t *ap = (uint32_t *)acc + 3 * node;
                 uint32_t *const ae = ap + 3 * (rhi - rlo + 1);
                 do {
