@@ -33,7 +33,10 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 LDS_PEAK_TOPS = 256 * 32 * 2.4e9 / 1e12     # 256 CUs x 32 banks x 2.4 GHz (dword ops)
 STAGES_FAST = ["bin_count", "scan", "eval", "scatter", "update"]
-KERNELS_FAST = ["k_bin_count", "k_scan", "k_eval", "k_scatter", "k_update"]
+# kernels of each stage (rocprofv3 names without template arguments)
+STAGE_KERNELS = {"bin_count": ["k_bin_count"], "scan": ["k_scan_reduce", "k_scan_down"],
+                 "eval": ["k_eval"], "scatter": ["k_scatter"],
+                 "update": ["k_gather_sorted", "k_update"]}
 WORKLOADS = {"c1": 1, "c2": 2, "c3": 3, "c3cube": 33, "c4": 4, "c5": 5}
 
 
@@ -98,9 +101,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel, launches_units):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, when they
-    were taken on the current kernel source; else None."""
+def traffic_from_profiles(stage):
+    """HBM bytes per launch of a stage's kernels from the committed rocprofv3
+    counter summary, when it was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -110,10 +113,12 @@ def traffic_from_profiles(kernel, launches_units):
         return None
     if data.get("kernel_sha") != kernel_source_hash():
         return None
-    ent = data.get("kernels", {}).get(kernel)
-    if not ent:
-        return None
-    return ent.get("bytes_per_launch")
+    total, found = 0.0, False
+    for name, ent in data.get("kernels", {}).items():
+        if name.split("<")[0] in STAGE_KERNELS[stage]:
+            total += ent.get("bytes_per_launch", 0.0)
+            found = True
+    return round(total) if found else None
 
 
 def main():
@@ -185,9 +190,9 @@ def main():
     dom_name = STAGES_FAST[dom]
     dom_bytes = kbytes.get(dom_name, 0)
     achieved = dom_bytes / (stage_ms[dom] * 1e-3) / 1e9
-    roof = {"kernel": KERNELS_FAST[dom], "bound": "hbm", "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_from_profiles(KERNELS_FAST[dom], None),
+    roof = {"kernel": "+".join(STAGE_KERNELS[dom_name]), "bound": "hbm",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(dom_name),
             "algorithmic_bytes_per_launch": dom_bytes,
             "avg_launch_us": round(stage_ms[dom] * 1e3, 2)}
     if dom_name == "scatter":

@@ -25,6 +25,14 @@ namespace erpp {
 
 namespace {
 
+// Logical block of a launch whose grid is padded to a multiple of kXcds:
+// physical block b runs on XCD b mod kXcds; XCD x takes logical blocks
+// [x G/kXcds, (x + 1) G/kXcds).  A bijection on [0, grid).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t grid) {
+    return (b % kXcds) * (grid / kXcds) + b / kXcds;
+}
+
 __device__ __forceinline__ int64_t cell_key(const DevBox &B, int b0, int b1, int b2) {
     return ((int64_t)b2 * B.n[1] + b1) * B.n[0] + b0;
 }
@@ -533,14 +541,20 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
 // particle.  x^n arrives in record order from the evaluation kernel; the FP64
 // trilinear value (plus the mean shear) is stored in record order too.
 __global__ void __launch_bounds__(kBlock) k_gather_sorted(const DevBox *__restrict__ Bs, int nbox,
+                                                          int64_t nblk,
                                                           const int64_t *__restrict__ stepp,
                                                           int M, const double4 *__restrict__ xs,
                                                           double4 *__restrict__ up) {
     const int64_t n = *stepp;
     if (n < M) return;
-    const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_p; });
+    // workgroups are dealt to the 8 XCDs round-robin; give each XCD (its own L2)
+    // one contiguous eighth of the records, so that neighbouring particles share
+    // the carrier lines they read
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    if (blk >= nblk) return;
+    const int bi = box_of_block(Bs, nbox, blk, [](const DevBox &b) { return b.blk_p; });
     const DevBox &B = Bs[bi];
-    const int64_t r = (int64_t)(blockIdx.x - B.blk_p) * kBlock + threadIdx.x;
+    const int64_t r = (blk - B.blk_p) * kBlock + threadIdx.x;
     if (r >= B.np) return;
     // the records of a box are [poff, poff + np): its cells follow the cells of
     // the boxes before it in the scanned key space
@@ -695,8 +709,10 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
             break;
         case 4:
             if (P->np_total > 0) {
-                hipLaunchKernelGGL(k_gather_sorted, dim3((unsigned)P->pblocks), dim3(kBlock), 0,
-                                   st, P->dbox, P->nbox, P->s.step + 1, P->M, P->s.xs, P->s.up);
+                const int64_t grid = (P->pblocks + kXcds - 1) / kXcds * kXcds;
+                hipLaunchKernelGGL(k_gather_sorted, dim3((unsigned)grid), dim3(kBlock), 0, st,
+                                   P->dbox, P->nbox, P->pblocks, P->s.step + 1, P->M, P->s.xs,
+                                   P->s.up);
                 hipLaunchKernelGGL(k_update, dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step + 1, P->M, P->dt, P->self_correction,
                                    P->s.up, P->s.sl);
