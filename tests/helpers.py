@@ -49,3 +49,52 @@ def periodic_diff(a, b, L):
     d = np.asarray(a) - np.asarray(b)
     Ls = np.asarray(L, dtype=np.float64)[:, None]
     return d - Ls * np.round(d / Ls)
+
+
+def window_particles(box, lo, wn, margin):
+    """Indices of the particles whose position lies within `margin` of the node
+    window [lo, lo + wn) (periodic), the only ones whose stencil can reach it."""
+    keep = np.ones(box.np_, bool)
+    for d in range(3):
+        c = (lo[d] + 0.5 * (wn[d] - 1)) * box.dx[d]
+        dd = box.x[d] - c
+        dd -= box.L[d] * np.round(dd / box.L[d])
+        keep &= np.abs(dd) <= 0.5 * (wn[d] - 1) * box.dx[d] + margin
+    return np.nonzero(keep)[0]
+
+
+def sampled_parity(box, db, M, dt, steps, precision, rng, nsample=4000, wn=(24, 24, 24),
+                   self_correction=1):
+    """Oracle on subsets after `steps` steps of the GPU path on the whole box.
+
+    The carrier is frozen, so particles are independent: the oracle run on a
+    subset reproduces that subset exactly.  (a) v and x of `nsample` random
+    particles; (b) the forcing of the last step on a node window, from every
+    particle that can reach it (3 sigma plus the largest drift over the run).
+    Returns (rel-L2 of v, max periodic |dx|, rel-L2 of f on the window)."""
+    import torch
+    P = oracle.params_for_box(box, M, dt, self_correction)
+    u = carrier_for(box, precision)
+    sample = rng.choice(box.np_, size=min(nsample, box.np_), replace=False)
+    run = oracle.Run(P, u, box.x[:, sample], box.v[:, sample], box.tau[sample])
+    for _ in range(steps):
+        run.step(want_f=False)
+    torch.cuda.synchronize()
+    ev = rel_l2(db.v.cpu().numpy()[:, sample], run.v)
+    ex = float(np.max(np.abs(periodic_diff(db.x.cpu().numpy()[:, sample], run.x, box.L))))
+    wn = tuple(min(wn[d], box.n[d]) for d in range(3))
+    lo = tuple(int(rng.integers(0, n)) for n in box.n)
+    vmax = float(np.max(np.abs(box.v))) + float(np.max(np.abs(box.u))) \
+        + abs(box.spec.shear) * box.L[1]
+    margin = box.spec.cutoff * box.sigma + 2.0 * vmax * steps * dt + 2 * max(box.dx)
+    idx = window_particles(box, lo, wn, margin)
+    run2 = oracle.Run(P, u, box.x[:, idx], box.v[:, idx], box.tau[idx])
+    for _ in range(steps - 1):
+        run2.step(want_f=False)
+    fo, _ = run2.step(want_f=True, lo=lo, wn=wn)
+    fg = db.f.double().cpu().numpy()
+    iz = (np.arange(wn[2]) + lo[2]) % box.n[2]
+    iy = (np.arange(wn[1]) + lo[1]) % box.n[1]
+    ix = (np.arange(wn[0]) + lo[0]) % box.n[0]
+    fw = fg[:, iz][:, :, iy][:, :, :, ix]
+    return ev, ex, rel_l2(fw, fo)
