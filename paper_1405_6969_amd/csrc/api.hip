@@ -62,6 +62,8 @@ void free_scratch(erpp_plan *p) {
     (void)hipFree(s.rank);
     (void)hipFree(s.rec);
     (void)hipFree(s.up);
+    (void)hipFree(s.bsum);
+    (void)hipFree(s.pscale);
     (void)hipFree(s.xs);
     (void)hipFree(s.sl);
     (void)hipFree(s.part);
@@ -89,7 +91,10 @@ hipError_t alloc(T **ptr, size_t count) {
 }
 
 erpp_status upload_boxes(erpp_plan *p) {
-    if (p->prec == ERPP_F32_FAST) HIP_OR_RETURN(erpp::fast_prepare_lds(p->lds_bytes));
+    if (p->prec == ERPP_F32_FAST) {
+        HIP_OR_RETURN(erpp::fast_prepare_lds(p->lds_bytes));
+        HIP_OR_RETURN(erpp::fast_prepare_bound_lds(p->bound_lds));
+    }
     HIP_OR_RETURN(hipMemcpy(p->dbox, p->hbox.data(), sizeof(erpp::DevBox) * p->hbox.size(),
                             hipMemcpyHostToDevice));
     return ERPP_OK;
@@ -152,8 +157,8 @@ static int32_t round4(int64_t v) { return (int32_t)((v + 3) & ~int64_t(3)); }
 // Pencils, block offsets and the scatter's LDS layout of every box for the
 // plan's tile.  Returns false when a pencil does not fit the LDS.
 bool fill_box_tiles(erpp_plan *p) {
-    int64_t cell = 0, key = 0, bp = 0, bt = 0, br = 0;
-    int64_t lds_max = 0;
+    int64_t cell = 0, key = 0, bp = 0, bt = 0, br = 0, bb = 0, rows = 0;
+    int64_t lds_max = 0, bound_max = 0;
     for (auto &B : p->hbox) {
         int32_t ext[3];
         for (int d = 0; d < 3; ++d) ext[d] = B.mhi[d] - B.mlo[d] + 1;
@@ -182,16 +187,24 @@ bool fill_box_tiles(erpp_plan *p) {
         B.pxa = B.n[0] + ext[0];
         const int64_t accw = 3 * (int64_t)B.T[2] * B.T[1] * B.pxa;
         B.lds_tab = round4(accw);
-        const int64_t tabw = (int64_t)(B.T[2] + ext[2] - 1) * (B.T[1] + ext[1] + 1);
+        const int64_t wy = B.T[1] + ext[1] - 1, wz = B.T[2] + ext[2] - 1;
+        const int64_t tabw = wz * (wy + 2);
         lds_max = std::max<int64_t>(lds_max, 4 * (B.lds_tab + round4(tabw)));
+        bound_max = std::max<int64_t>(bound_max, 4 * wz * wy * kBoundXChunk);
+        B.blk_b = bb;
+        bb += ((int64_t)B.nxb * B.n[1] * B.n[2] + kBlock - 1) / kBlock;
+        rows += (int64_t)B.n[1] * B.n[2];
     }
     p->ncell_total = cell;
     p->nkey_total = key;
+    p->nrows_total = rows;
+    p->bblocks = bb;
     p->pblocks = bp;
     p->tblocks = bt;
     p->pblocks_rows = br;
     p->lds_bytes = (size_t)lds_max;
-    return p->lds_bytes <= kMaxScatterLds;
+    p->bound_lds = (size_t)bound_max;
+    return p->lds_bytes <= kMaxScatterLds && p->bound_lds <= kMaxScatterLds;
 }
 
 }  // namespace erpp
@@ -316,6 +329,8 @@ erpp_status erpp_plan_create(erpp_plan **out, const erpp_box *boxes, int32_t nbo
               alloc(&p->s.rank, (size_t)np_total) == hipSuccess;
     if (ok && prec == ERPP_F32_FAST)
         ok = alloc(&p->s.rec, 2 * (size_t)np_total) == hipSuccess &&
+             alloc(&p->s.bsum, (size_t)std::max<int64_t>(p->nkey_total, 1)) == hipSuccess &&
+             alloc(&p->s.pscale, (size_t)std::max<int64_t>(p->nrows_total, 1)) == hipSuccess &&
              alloc(&p->s.up, (size_t)np_total) == hipSuccess &&
              alloc(&p->s.xs, (size_t)np_total) == hipSuccess &&
              alloc(&p->s.sl, (size_t)np_total) == hipSuccess;

@@ -18,6 +18,7 @@ constexpr int kScatterBlock = 512;   // threads per block of the tiled scatter
 constexpr int kScatterWaves = kScatterBlock / 64;
 constexpr int kScanChunk = 4096;     // counters per block of the device-wide scan
 constexpr int kXBlockShift = 4;      // step binning: x-blocks of 16 cells per cell row
+constexpr int kBoundXChunk = 16;     // x-blocks per LDS pass of the pencil-scale kernel
 
 // Everything a kernel needs to know about one box; lives in device memory as
 // an array indexed by box.  Plain old data.
@@ -37,6 +38,7 @@ struct DevBox {
     int32_t pad0;
     int64_t blk_p;       // first block of this box in particle launches
     int64_t blk_t;       // first block of this box in tile launches
+    int64_t blk_b;       // first block of this box in (cell row, x-block) launches
     int64_t blk_r;       // first block of this box in (particle, row) launches
     int64_t rows;        // stencil rows (my, mz) per particle
     double L[3];
@@ -69,6 +71,8 @@ struct Scratch {
     int32_t *ticket = nullptr;   // [1]             scan: workgroups done (zero at rest)
     int32_t *rank = nullptr;     // [np_total]      rank of a particle inside its cell
     float4 *rec = nullptr;       // [2*np_total]    cell-sorted injection records
+    float *bsum = nullptr;       // [nkey_total]    max_c |amplitude| summed over x-blocks X-1..X+1
+    float *pscale = nullptr;     // [sum Ny Nz]     fixed-point scale of each scatter pencil
     double4 *xs = nullptr;       // [np_total]      x^n in record order
     double4 *up = nullptr;       // [np_total]      carrier at x^n in record order (FP64)
     int32_t *sl = nullptr;       // [np_total]      record slot of each particle
@@ -100,9 +104,12 @@ struct erpp_plan {
     int64_t nkey_total = 0;
     int64_t pblocks = 0;         // blocks of particle launches (box aligned)
     int64_t tblocks = 0;         // blocks of tile launches
+    int64_t bblocks = 0;         // blocks of (cell row, x-block) launches
+    int64_t nrows_total = 0;     // cell rows (y, z) of all boxes: the most pencils possible
     int64_t pblocks_rows = 0;    // plain scatter: blocks over (particle,row)
     erpp::Scratch s;
     size_t lds_bytes = 0;
+    size_t bound_lds = 0;        // dynamic LDS of the pencil-scale kernel
     // graph of one step (step index read from s.step)
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -126,6 +133,6 @@ bool fill_box_tiles(erpp_plan *p);          // tiles, blocks, LDS layout; false 
 hipError_t scan_counts(int32_t *count, int64_t n, int32_t *start, int32_t *part, int32_t *ticket,
                        int64_t *stepp, hipStream_t st);
 hipError_t fast_prepare_lds(size_t bytes);         // opt the scatter into > 64 KB LDS
+hipError_t fast_prepare_bound_lds(size_t bytes);   // same for the pencil-scale kernel
 constexpr size_t kMaxScatterLds = 150 * 1024;
-constexpr size_t kScatterLdsTarget = 74 * 1024;   // two workgroups per CU (with static LDS)
 }  // namespace erpp

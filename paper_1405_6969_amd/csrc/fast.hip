@@ -262,11 +262,136 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
     sl[B.poff + p] = (int32_t)slotr;
 }
 
-// --------------------------------------------------------------- scatter ----
 __device__ __forceinline__ int wrap_index(int i, int N) {
     i %= N;
     return i < 0 ? i + N : i;
 }
+
+// --------------------------------------------------------- scatter bound ----
+// Fixed-point range of each scatter pencil.  A node in x-block X (16 cells, at
+// least the stencil half-width) receives only from particles in x-blocks
+// X-1..X+1 of the cell rows its row classes reach, each at most max_c |a| (the
+// raw Gaussian is <= 1).  k_block_sums: for every cell row and x-block, the sum
+// of max_c |a| over the records of blocks X-1..X+1 (periodic).  k_pencil_scale:
+// for every pencil, the largest sum over (pencil row, X) of those entries over
+// the reachable row classes bounds |f| on the pencil; its scale is 2^30 / bound.
+__device__ __forceinline__ float rec_amax(const float4 *__restrict__ rec, int64_t r) {
+    const float4 b = rec[2 * r + 1];
+    return fmaxf(fabsf(b.x), fmaxf(fabsf(b.y), fabsf(b.z)));
+}
+
+__global__ void __launch_bounds__(kBlock) k_block_sums(const DevBox *__restrict__ Bs, int nbox,
+                                                       const int64_t *__restrict__ stepp, int M,
+                                                       const int32_t *__restrict__ start,
+                                                       const float4 *__restrict__ rec,
+                                                       float *__restrict__ bsum) {
+    if (*stepp < M) return;
+    const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_b; });
+    const DevBox &B = Bs[bi];
+    const int64_t e = (int64_t)(blockIdx.x - B.blk_b) * kBlock + threadIdx.x;
+    const int nxb = B.nxb;
+    if (e >= (int64_t)B.n[1] * B.n[2] * nxb) return;
+    const int X = (int)(e % nxb);
+    const int64_t row = B.key_off + (e - X);     // first key of the cell row
+    float s = 0.0f;
+    for (int k = -1; k <= 1; ++k) {
+        int Xk = X + k;
+        Xk += (Xk < 0) ? nxb : 0;
+        Xk -= (Xk >= nxb) ? nxb : 0;
+        const int g1 = start[row + Xk + 1];
+        for (int g = start[row + Xk]; g < g1; ++g) s += rec_amax(rec, g);
+    }
+    bsum[B.key_off + e] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_pencil_scale(const DevBox *__restrict__ Bs, int nbox,
+                                                         const int64_t *__restrict__ stepp, int M,
+                                                         const float *__restrict__ bsum,
+                                                         float *__restrict__ pscale) {
+    if (*stepp < M) return;
+    extern __shared__ float win[];              // [WZ][WY][kBoundXChunk] of bsum
+    __shared__ int s_dy[256], s_dz[256];
+    __shared__ int s_ncls;
+    __shared__ float s_max[kBlock / 64];
+    const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_t; });
+    const DevBox &B = Bs[bi];
+    const int t = (int)(blockIdx.x - B.blk_t);
+    const int T1 = B.T[1], T2 = B.T[2];
+    const int o1 = (t % B.ntile[1]) * T1;
+    const int o2 = (t / B.ntile[1]) * T2;
+    const int Ny = B.n[1], Nz = B.n[2], nxb = B.nxb;
+    const int e1 = min(T1, Ny - o1);
+    const int e2 = min(T2, Nz - o2);
+    const int mlo1 = B.mlo[1], mhi1 = B.mhi[1], mlo2 = B.mlo[2], mhi2 = B.mhi[2];
+    const int ny = mhi1 - mlo1 + 1, nz = mhi2 - mlo2 + 1;
+    const int WY = e1 + mhi1 - mlo1, WZ = e2 + mhi2 - mlo2;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_ncls = 0;
+    __syncthreads();
+    for (int k = tid; k < ny * nz; k += kBlock) {
+        const int dy = mlo1 + k % ny, dz = mlo2 + k / ny;
+        const float ay = (float)(dy >= 1 ? dy - 1 : -dy) * B.dxf[1];
+        const float az = (float)(dz >= 1 ? dz - 1 : -dz) * B.dxf[2];
+        if (fmaf(ay, ay, az * az) <= B.R2f + B.guard) {
+            const int i = atomicAdd(&s_ncls, 1);
+            s_dy[i] = dy;
+            s_dz[i] = dz;
+        }
+    }
+    __syncthreads();
+    const int ncls = s_ncls;
+    float bmax = 0.0f;
+    for (int X0 = 0; X0 < nxb; X0 += kBoundXChunk) {
+        const int nx = min(kBoundXChunk, nxb - X0);
+        // window cell rows b1 = o1 - mhi1 + wy, b2 = o2 - mhi2 + wz (periodic)
+        for (int k = tid; k < WZ * WY * nx; k += kBlock) {
+            const int X = k % nx, r = k / nx;
+            const int wy = r % WY, wz = r / WY;
+            int b1 = o1 - mhi1 + wy, b2 = o2 - mhi2 + wz;
+            b1 += (b1 < 0) ? Ny : 0;
+            b1 -= (b1 >= Ny) ? Ny : 0;
+            b2 += (b2 < 0) ? Nz : 0;
+            b2 -= (b2 >= Nz) ? Nz : 0;
+            win[r * kBoundXChunk + X] = bsum[B.key_off + ((int64_t)b2 * Ny + b1) * nxb + X0 + X];
+        }
+        if (nx < kBoundXChunk)
+            for (int k = tid; k < WZ * WY * (kBoundXChunk - nx); k += kBlock) {
+                const int X = nx + k % (kBoundXChunk - nx), r = k / (kBoundXChunk - nx);
+                win[r * kBoundXChunk + X] = 0.0f;
+            }
+        __syncthreads();
+        // four x-blocks per thread (128-bit LDS reads; entries past nx are zero)
+        const int nq = (nx + 3) / 4;
+        for (int k = tid; k < e1 * e2 * nq; k += kBlock) {
+            const int Xq = k % nq, r = k / nq;
+            const int y = r % e1, z = r / e1;
+            float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 8
+            for (int ci = 0; ci < ncls; ++ci) {
+                const float4 v = *(const float4 *)&win[((z + mhi2 - s_dz[ci]) * WY +
+                                                        (y + mhi1 - s_dy[ci])) * kBoundXChunk +
+                                                       4 * Xq];
+                sum.x += v.x;
+                sum.y += v.y;
+                sum.z += v.z;
+                sum.w += v.w;
+            }
+            bmax = fmaxf(bmax, fmaxf(fmaxf(sum.x, sum.y), fmaxf(sum.z, sum.w)));
+        }
+        __syncthreads();
+    }
+    for (int off = 32; off > 0; off >>= 1) bmax = fmaxf(bmax, __shfl_xor(bmax, off, 64));
+    if ((tid & 63) == 0) s_max[tid >> 6] = bmax;
+    __syncthreads();
+    if (tid == 0) {
+        float bound = 0.0f;
+        for (int w = 0; w < kBlock / 64; ++w) bound = fmaxf(bound, s_max[w]);
+        bound *= 1.0001f;   // margin for the FP32 roundings of the sums
+        pscale[blockIdx.x] = (bound > 0.0f && bound < 3.0e38f) ? 1073741824.0f / bound : 1.0f;
+    }
+}
+
+// --------------------------------------------------------------- scatter ----
 
 // Contribution to the integer tile: v_cvt_rpi_i32_f32 rounds to floor(v + 0.5)
 // in one instruction (|v| < 2^30 by the choice of scale; the error of one term
@@ -299,11 +424,11 @@ __device__ __forceinline__ uint32_t fixed32(float v) {
 // words, and the store folds the ends back onto the periodic row.
 //
 // Accumulation is exact integer arithmetic: each contribution a*w is rounded to
-// an int32 with the per-pencil scale 2^30 / A, where A = sum over the pencil's
-// particle window of max_c |amplitude| bounds |f| at every node of the pencil
-// (the raw Gaussian is <= 1), and added with ds_add_u32 (the FP32 LDS atomic
-// runs ~40x slower on gfx950).  Integer additions commute, so the forcing does
-// not depend on the order of the adds.
+// an int32 with the per-pencil scale 2^30 / A, where A bounds the sum of |a w|
+// over the contributions to any node of the pencil (k_pencil_scale), and
+// added with ds_add_u32 (the FP32 LDS atomic runs ~40x slower on gfx950).
+// Integer additions commute, so the forcing does not depend on the order of the
+// adds.
 // TZ: the plan's pencil depth rounded up to a power of two (>= every box's T2);
 // a row class has at most 2 TZ record ranges.
 template <int TZ>
@@ -312,12 +437,11 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
                                                            const int64_t *__restrict__ stepp,
                                                            int M,
                                                            const int32_t *__restrict__ start,
-                                                           const float4 *__restrict__ rec) {
+                                                           const float4 *__restrict__ rec,
+                                                           const float *__restrict__ pscale) {
     extern __shared__ int32_t lds[];
     __shared__ int s_cls[256];
     __shared__ int s_ncls;
-    __shared__ float s_part[kScatterWaves];
-    __shared__ float s_scale;
     const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_t; });
     const DevBox &B = Bs[bi];
     const int t = (int)(blockIdx.x - B.blk_t);
@@ -378,30 +502,8 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
                 h1 = T[ja + len];
             }
         };
-        // ---- amplitude bound of the pencil (fixed-order reduction)
-        float part = 0.0f;
-        for (int wz = 0; wz < WZ; ++wz) {
-            int g0, g1, h0, h1;
-            ranges(wz, 0, WY, g0, g1, h0, h1);
-            for (int g = g0 + tid; g < g1; g += kScatterBlock) {
-                const float4 qb = rec[2 * (int64_t)g + 1];
-                part += fmaxf(fabsf(qb.x), fmaxf(fabsf(qb.y), fabsf(qb.z)));
-            }
-            for (int g = h0 + tid; g < h1; g += kScatterBlock) {
-                const float4 qb = rec[2 * (int64_t)g + 1];
-                part += fmaxf(fabsf(qb.x), fmaxf(fabsf(qb.y), fabsf(qb.z)));
-            }
-        }
-        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-        if (lane == 0) s_part[wv] = part;
-        __syncthreads();
-        if (tid == 0) {
-            float bound = 0.0f;
-            for (int w = 0; w < kScatterWaves; ++w) bound += s_part[w];
-            s_scale = (bound > 0.0f && bound < 3.0e38f) ? 1073741824.0f / bound : 1.0f;
-        }
-        __syncthreads();
-        scale = s_scale;
+        // fixed-point scale of the pencil (k_pencil_scale)
+        scale = pscale[blockIdx.x];
         const int64_t slot = (n - M) % (M + 1);
         const float hx = B.dxf[0], hy = B.dxf[1], hz = B.dxf[2];
         const float c = B.cexp;
@@ -671,6 +773,11 @@ hipError_t scan_counts(int32_t *count, int64_t n, int32_t *start, int32_t *part,
     return hipGetLastError();
 }
 
+hipError_t fast_prepare_bound_lds(size_t bytes) {
+    return hipFuncSetAttribute((const void *)k_pencil_scale,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 hipError_t fast_prepare_lds(size_t bytes) {
     const void *fns[] = {(const void *)k_scatter<1>, (const void *)k_scatter<2>,
                          (const void *)k_scatter<4>, (const void *)k_scatter<8>};
@@ -702,9 +809,15 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                 const int tz = P->tile[2];
                 auto fn = tz <= 1 ? k_scatter<1> : tz <= 2 ? k_scatter<2>
                                                  : tz <= 4 ? k_scatter<4> : k_scatter<8>;
+                hipLaunchKernelGGL(k_block_sums, dim3((unsigned)P->bblocks), dim3(kBlock), 0, st,
+                                   P->dbox, P->nbox, P->s.step + 1, P->M, P->s.start, P->s.rec,
+                                   P->s.bsum);
+                hipLaunchKernelGGL(k_pencil_scale, dim3((unsigned)P->tblocks), dim3(kBlock),
+                                   P->bound_lds, st, P->dbox, P->nbox, P->s.step + 1, P->M,
+                                   P->s.bsum, P->s.pscale);
                 hipLaunchKernelGGL(fn, dim3((unsigned)P->tblocks), dim3(kScatterBlock),
                                    P->lds_bytes, st, P->dbox, P->nbox, P->s.step + 1, P->M,
-                                   P->s.start, P->s.rec);
+                                   P->s.start, P->s.rec, P->s.pscale);
             }
             break;
         case 4:
