@@ -35,7 +35,7 @@ LDS_PEAK_TOPS = 256 * 32 * 2.4e9 / 1e12     # 256 CUs x 32 banks x 2.4 GHz (dwor
 STAGES_FAST = ["bin_count", "scan", "eval", "scatter", "update"]
 # kernels of each stage (rocprofv3 names without template arguments)
 STAGE_KERNELS = {"bin_count": ["k_bin_count"], "scan": ["k_scan_reduce", "k_scan_down"],
-                 "eval": ["k_eval"], "scatter": ["k_scatter"],
+                 "eval": ["k_eval"], "scatter": ["k_block_sums", "k_pencil_scale", "k_scatter"],
                  "update": ["k_gather_sorted", "k_update"]}
 WORKLOADS = {"c1": 1, "c2": 2, "c3": 3, "c3cube": 33, "c4": 4, "c5": 5}
 
