@@ -108,9 +108,10 @@ __global__ void __launch_bounds__(256) k_scan_reduce(const int32_t *__restrict__
     __shared__ int s_last;
     const int64_t base = (int64_t)blockIdx.x * kScanChunk;
     int s = 0;
+#pragma unroll
     for (int j = 0; j < kScanChunk / 256; ++j) {
         const int64_t i = base + j * 256 + threadIdx.x;
-        if (i < n) s += count[i];
+        s += (i < n) ? count[i] : 0;
     }
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = s;
@@ -154,15 +155,18 @@ __global__ void __launch_bounds__(256) k_scan_down(int32_t *__restrict__ count, 
     __shared__ int sw[4];
     const int64_t base = (int64_t)blockIdx.x * kScanChunk;
     const int t = threadIdx.x;
+    int cv[kScanChunk / 256];
+#pragma unroll
+    for (int j = 0; j < kScanChunk / 256; ++j) {
+        const int64_t i = base + j * 256 + t;
+        cv[j] = (i < n) ? count[i] : 0;
+    }
+#pragma unroll
     for (int j = 0; j < kScanChunk / 256; ++j) {
         const int k = j * 256 + t;
         const int64_t i = base + k;
-        int c = 0;
-        if (i < n) {
-            c = count[i];
-            count[i] = 0;
-        }
-        buf[k + (k >> 4)] = c;
+        if (i < n) count[i] = 0;
+        buf[k + (k >> 4)] = cv[j];
     }
     __syncthreads();
     int s = 0;
@@ -194,12 +198,47 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
                                                  double4 *__restrict__ xs,
                                                  int32_t *__restrict__ sl) {
     __shared__ float sP[kMaxOff + 1][kBlock];   // prefix sums of the x factors
+    __shared__ int s_cls[256];                   // reachable row classes, (dz, dy) order
+    __shared__ int s_wcnt[kBlock / 64];
     const int64_t n = *stepp;
     if (n < M) return;
     const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_p; });
     const DevBox &B = Bs[bi];
     const int tid = threadIdx.x;
     const int64_t p = (int64_t)(blockIdx.x - B.blk_p) * kBlock + tid;
+    const float cut = B.R2f + B.guard;
+    // row classes (my, mz) whose row can meet the sphere for some offset in the
+    // cell: a deterministic compaction (ballot ranks + wave counts), so the sum
+    // order of Z is fixed
+    const int mlo1 = B.mlo[1], ny = B.mhi[1] - B.mlo[1] + 1;
+    const int mlo2 = B.mlo[2], nz = B.mhi[2] - B.mlo[2] + 1;
+    int ncls = 0;
+    for (int c0 = 0; c0 < ny * nz; c0 += kBlock) {
+        const int k = c0 + tid;
+        bool reach = false;
+        if (k < ny * nz) {
+            const int dy = mlo1 + k % ny, dz = mlo2 + k / ny;
+            const float ay = (float)(dy >= 1 ? dy - 1 : -dy) * B.dxf[1];
+            const float az = (float)(dz >= 1 ? dz - 1 : -dz) * B.dxf[2];
+            reach = fmaf(ay, ay, az * az) <= cut;
+        }
+        const uint64_t mask = __ballot(reach);
+        const int lane = tid & 63, w = tid >> 6;
+        if (lane == 0) s_wcnt[w] = __popcll(mask);
+        __syncthreads();
+        int before = ncls, total = ncls;
+        for (int q = 0; q < kBlock / 64; ++q) {
+            before += (q < w) ? s_wcnt[q] : 0;
+            total += s_wcnt[q];
+        }
+        if (reach) {
+            // packed offsets (my + 512) | (mz + 512) << 10: no division per row
+            const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+            s_cls[before + rank] = (mlo1 + k % ny + 512) | ((mlo2 + k / ny + 512) << 10);
+        }
+        ncls = total;
+        __syncthreads();
+    }
     if (p >= B.np) return;
     const int64_t np = B.np;
     const int64_t slot = (n - M) % (M + 1);
@@ -209,10 +248,14 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
     double ph[3];
     for (int d = 0; d < 3; ++d) cell_of(X[d * np + p], B.L[d], B.dx[d], B.n[d], b[d], ph[d]);
     const float phx = (float)ph[0], phy = (float)ph[1], phz = (float)ph[2];
+    // loads needed after the normalisation, issued now so that their latency
+    // overlaps it
+    const int32_t sk = start[step_key(B, b[0], b[1], b[2])];
+    const int32_t rk = rank[B.poff + p];
+    const float D0 = Dd[p], D1 = Dd[np + p], D2 = Dd[2 * np + p];
+    const double x0 = B.x[p], x1 = B.x[np + p], x2 = B.x[2 * np + p];
     const int mlo0 = B.mlo[0], mhi0 = B.mhi[0];
-    const int mlo1 = B.mlo[1], ny = B.mhi[1] - B.mlo[1] + 1;
-    // prefix sums of the x factors (indexed by row ends: LDS); y factors and
-    // offsets in registers (row loop unrolled over the maximum stencil width)
+    // prefix sums of the x factors (indexed by the row ends)
     sP[0][tid] = 0.0f;
     {
         float acc = 0.0f;
@@ -221,44 +264,31 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
             sP[m - mlo0 + 1][tid] = acc;
         }
     }
-    float gy[kMaxOff], ty[kMaxOff];
-#pragma unroll
-    for (int j = 0; j < kMaxOff; ++j) {
-        gy[j] = (j < ny) ? g1(mlo1 + j, phy, B.dxf[1], B.cexp) : 0.0f;
-        ty[j] = (j < ny) ? d1(mlo1 + j, phy, B.dxf[1]) : 0.0f;
-    }
-    const float cut = B.R2f + B.guard;
     const int pid = (int)p;
     float Z = 0.0f;
-    for (int mz = B.mlo[2]; mz <= B.mhi[2]; ++mz) {
+    for (int ci = 0; ci < ncls; ++ci) {
+        const int k = s_cls[ci];
+        const int my = (k & 1023) - 512, mz = (k >> 10) - 512;
+        const float ty = d1(my, phy, B.dxf[1]);
         const float tz = d1(mz, phz, B.dxf[2]);
-        const float tz2 = tz * tz;
-        if (tz2 > cut) continue;
-        const float gz = g1(mz, phz, B.dxf[2], B.cexp);
-        float Zp = 0.0f;
-#pragma unroll
-        for (int j = 0; j < kMaxOff; ++j) {
-            if (j < ny) {
-                const float ryz = fmaf(ty[j], ty[j], tz2);
-                if (ryz <= cut) {
-                    int lo, hi;
-                    row_range(phx, ryz, B, &B, slot, pid, mlo1 + j, mz, lo, hi);
-                    if (lo <= hi) Zp = fmaf(gy[j], sP[hi - mlo0 + 1][tid] - sP[lo - mlo0][tid], Zp);
-                }
-            }
-        }
-        Z = fmaf(gz, Zp, Z);
+        const float ryz = fmaf(ty, ty, tz * tz);
+        if (ryz > cut) continue;
+        int lo, hi;
+        row_range(phx, ryz, B, &B, slot, pid, my, mz, lo, hi);
+        if (lo > hi) continue;
+        // y-z factor of the row: raw v_exp_f32 of -ryz c (in [-R^2 c, 0])
+        Z = fmaf(__builtin_amdgcn_exp2f(-ryz * B.cexp),
+                 sP[hi - mlo0 + 1][tid] - sP[lo - mlo0][tid], Z);
     }
     const float Zv = Z * (float)B.dV;
     const float inv = -B.rhof_inv / Zv;
-    const float ax = Dd[p] * inv, ay = Dd[np + p] * inv, az = Dd[2 * np + p] * inv;
-    const int64_t slotr =
-        (int64_t)start[step_key(B, b[0], b[1], b[2])] + rank[B.poff + p];
+    const float ax = D0 * inv, ay = D1 * inv, az = D2 * inv;
+    const int64_t slotr = (int64_t)sk + rk;
     const uint32_t ijk = (uint32_t)b[0] | ((uint32_t)b[1] << 11) | ((uint32_t)b[2] << 22);
     rec[2 * slotr] = make_float4(phx, phy, phz, __uint_as_float(ijk));
     rec[2 * slotr + 1] = make_float4(ax, ay, az, __int_as_float((int)p));
     // the current position x^n, in record order for the carrier gather
-    xs[slotr] = make_double4(B.x[p], B.x[np + p], B.x[2 * np + p], 0.0);
+    xs[slotr] = make_double4(x0, x1, x2, 0.0);
     sl[B.poff + p] = (int32_t)slotr;
 }
 
@@ -293,14 +323,19 @@ __global__ void __launch_bounds__(kBlock) k_block_sums(const DevBox *__restrict_
     if (e >= (int64_t)B.n[1] * B.n[2] * nxb) return;
     const int X = (int)(e % nxb);
     const int64_t row = B.key_off + (e - X);     // first key of the cell row
-    float s = 0.0f;
-    for (int k = -1; k <= 1; ++k) {
-        int Xk = X + k;
+    int g0[3], g1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        int Xk = X + k - 1;
         Xk += (Xk < 0) ? nxb : 0;
         Xk -= (Xk >= nxb) ? nxb : 0;
-        const int g1 = start[row + Xk + 1];
-        for (int g = start[row + Xk]; g < g1; ++g) s += rec_amax(rec, g);
+        g0[k] = start[row + Xk];
+        g1[k] = start[row + Xk + 1];
     }
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        for (int g = g0[k]; g < g1[k]; ++g) s += rec_amax(rec, g);
     bsum[B.key_off + e] = s;
 }
 
