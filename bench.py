@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
-    ap.add_argument("--tile", default=None, help="tile as X,Y,Z (skips the autotuner)")
+    ap.add_argument("--tile", default=None,
+                    help="scatter shape THREADS,T1,T2 (skips the autotuner)")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true")

@@ -106,14 +106,14 @@ erpp_status erpp_plan_create(erpp_plan **plan, const erpp_box *boxes, int32_t nb
                              int32_t M, double dt, erpp_precision precision,
                              int32_t self_correction, void *stream);
 
-/* Scatter pencil of an ERPP_F32_FAST plan: one workgroup owns all Nx nodes of
- * tile[1] x tile[2] grid rows (y, z).  tile[0] is ignored (stored as 0: a pencil
- * always spans the box in x); tile[1] in [1, 64], tile[2] in [1, 8].  Per box
- * the pencil is clipped so that a stencil never wraps onto it twice.  The LDS
- * copy of the pencil (12 bytes per node, rows unwrapped by the stencil width)
- * plus the window's record table must fit 150 KiB for every box of the plan;
- * otherwise ERPP_EINVAL and the plan keeps its pencil.  Invalidates a captured
- * graph. */
+/* Scatter decomposition of an ERPP_F32_FAST plan: one workgroup owns a pencil,
+ * all Nx nodes of tile[1] x tile[2] grid rows (y, z).  tile[0] is the number of
+ * threads per scatter workgroup, 512 or 1024 (0 selects 512); tile[1] in
+ * [1, 64], tile[2] in [1, 8].  Per box the pencil is clipped so that a stencil
+ * never wraps onto it twice.  The LDS copy of the pencil (12 bytes per node,
+ * rows unwrapped by the stencil width) plus the window's record table must fit
+ * 150 KiB for every box of the plan; otherwise ERPP_EINVAL and the plan keeps
+ * its shape.  Invalidates a captured graph. */
 erpp_status erpp_plan_set_tile(erpp_plan *plan, const int32_t tile[3]);
 erpp_status erpp_plan_get_tile(const erpp_plan *plan, int32_t tile[3]);
 

@@ -115,7 +115,9 @@ erpp_status alloc_bins(erpp_plan *p) {
 
 erpp_status check_tile(const int32_t tile[3]) {
     if (!tile) return fail(ERPP_EINVAL, "tile is NULL");
-    if (tile[0] < 0) return fail(ERPP_EINVAL, "tile[0]=%d < 0", tile[0]);
+    if (tile[0] != 0 && tile[0] != 512 && tile[0] != 1024)
+        return fail(ERPP_EINVAL, "tile[0]=%d: scatter workgroup threads must be 0, 512 or 1024",
+                    tile[0]);
     if (tile[1] < 1 || tile[1] > erpp::kMaxTileY)
         return fail(ERPP_EINVAL, "tile[1]=%d outside [1, %d]", tile[1], erpp::kMaxTileY);
     if (tile[2] < 1 || tile[2] > erpp::kMaxTileZ)
@@ -364,7 +366,7 @@ erpp_status erpp_plan_set_tile(erpp_plan *p, const int32_t tile[3]) {
     int32_t old[3];
     for (int d = 0; d < 3; ++d) {
         old[d] = p->tile[d];
-        p->tile[d] = d == 0 ? 0 : tile[d];
+        p->tile[d] = (d == 0 && tile[0] == 0) ? 512 : tile[d];
     }
     if (!erpp::fill_box_tiles(p)) {
         const size_t need = p->lds_bytes;
@@ -483,7 +485,7 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
     hipStream_t st = as_stream(stream);
     // geometry key
     std::ostringstream key;
-    key << "v4 M" << p->M << " nbox" << p->nbox;
+    key << "v5 M" << p->M << " nbox" << p->nbox;
     for (const auto &B : p->hbox)
         key << " " << B.n[0] << "x" << B.n[1] << "x" << B.n[2] << ":" << B.np << ":" << B.mlo[0]
             << "," << B.mhi[0];
@@ -500,9 +502,10 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
                 return erpp_plan_set_tile(p, t);
         }
     }
-    static const int32_t cand[][3] = {{0, 16, 1}, {0, 8, 2}, {0, 8, 1}, {0, 4, 4},
-                                      {0, 4, 2}, {0, 32, 1}, {0, 16, 2}, {0, 2, 2},
-                                      {0, 4, 1}, {0, 2, 4}, {0, 1, 2}, {0, 8, 4}};
+    static const int32_t cand[][3] = {{512, 16, 1},  {512, 8, 2},   {512, 8, 1},  {512, 4, 4},
+                                      {512, 4, 2},   {512, 32, 1},  {512, 2, 2},  {512, 4, 1},
+                                      {1024, 32, 1}, {1024, 16, 2}, {1024, 16, 1}, {1024, 8, 4},
+                                      {1024, 64, 1}, {1024, 8, 2}};
     const int ncand = (int)(sizeof cand / sizeof cand[0]);
     int32_t best[3] = {p->tile[0], p->tile[1], p->tile[2]};
     float best_ms = 1e30f;

@@ -14,8 +14,6 @@ namespace erpp {
 constexpr int kMaxTileY = 64;        // scatter pencil: T1 x T2 nodes in (y, z), all of x
 constexpr int kMaxTileZ = 8;
 constexpr int kBlock = 256;          // threads per block of particle kernels
-constexpr int kScatterBlock = 512;   // threads per block of the tiled scatter
-constexpr int kScatterWaves = kScatterBlock / 64;
 constexpr int kScanChunk = 4096;     // counters per block of the device-wide scan
 constexpr int kXBlockShift = 4;      // step binning: x-blocks of 16 cells per cell row
 constexpr int kBoundXChunk = 16;     // x-blocks per LDS pass of the pencil-scale kernel
@@ -95,7 +93,7 @@ struct erpp_plan {
     double dt = 0;
     erpp_precision prec = ERPP_F32_FAST;
     int32_t self_correction = 1;
-    int32_t tile[3] = {0, 4, 4};     // scatter pencil: [0] unused (all of x), T1, T2
+    int32_t tile[3] = {512, 4, 4};   // scatter: [0] threads per workgroup, pencil T1, T2
     std::vector<erpp_box> boxes;
     std::vector<erpp::DevBox> hbox;
     erpp::DevBox *dbox = nullptr;

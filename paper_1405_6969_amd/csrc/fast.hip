@@ -465,9 +465,9 @@ __device__ __forceinline__ uint32_t fixed32(float v) {
 // Integer additions commute, so the forcing does not depend on the order of the
 // adds.
 // TZ: the plan's pencil depth rounded up to a power of two (>= every box's T2);
-// a row class has at most 2 TZ record ranges.
-template <int TZ>
-__global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restrict__ Bs,
+// a row class has at most 2 TZ record ranges.  NT: threads per workgroup.
+template <int TZ, int NT>
+__global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
                                                            int nbox,
                                                            const int64_t *__restrict__ stepp,
                                                            int M,
@@ -493,7 +493,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
     const int mlo0 = B.mlo[0], mhi0 = B.mhi[0];
     const int mlo1 = B.mlo[1], mhi1 = B.mhi[1];
     const int mlo2 = B.mlo[2], mhi2 = B.mhi[2];
-    for (int i = tid; i < 3 * T2 * T1 * PXa; i += kScatterBlock) acc[i] = 0;
+    for (int i = tid; i < 3 * T2 * T1 * PXa; i += NT) acc[i] = 0;
     const int64_t n = *stepp;
     float scale = 1.0f;
     if (n >= M) {
@@ -502,7 +502,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
         const int TW = WY + 2;                // table row: WY + 1 row starts, then end of plane
         // tab[wz][j] = first record of cell row b1 = (o1 - mhi1 + j) mod Ny of window
         // plane b2 = (o2 - mhi2 + wz) mod Nz, j <= WY; tab[wz][WY + 1] = end of the plane
-        for (int k = tid; k < WZ * TW; k += kScatterBlock) {
+        for (int k = tid; k < WZ * TW; k += NT) {
             const int wz = k / TW, j = k - wz * TW;
             const int b2 = wrap_index(o2 - mhi2 + wz, Nz);
             const int64_t plane = B.key_off + (int64_t)b2 * Ny * B.nxb;
@@ -545,7 +545,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
         const float qx = exp2f(-2.0f * c * hx * hx);
         const int ncls = s_ncls;
         const int nr = 2 * e2;
-        for (int ci = wv; ci < ncls; ci += kScatterWaves) {
+        for (int ci = wv; ci < ncls; ci += NT / 64) {
             const int cl = s_cls[ci];
             const int dy = mlo1 + cl % ny, dz = mlo2 + cl / ny;
             // lane k < 2 e2: part (k & 1) of the records of plane k >> 1.  Part 0
@@ -645,7 +645,7 @@ __global__ void __launch_bounds__(kScatterBlock) k_scatter(const DevBox *__restr
     const float inv = 1.0f / scale;
     const int64_t ng = (int64_t)Nx * Ny * Nz;
     const int cnt = Nx * e1 * e2;
-    for (int i = tid; i < cnt; i += kScatterBlock) {
+    for (int i = tid; i < cnt; i += NT) {
         const int x = i % Nx;
         const int r = i / Nx;
         const int ly = r % e1, lz = r / e1;
@@ -814,8 +814,10 @@ hipError_t fast_prepare_bound_lds(size_t bytes) {
 }
 
 hipError_t fast_prepare_lds(size_t bytes) {
-    const void *fns[] = {(const void *)k_scatter<1>, (const void *)k_scatter<2>,
-                         (const void *)k_scatter<4>, (const void *)k_scatter<8>};
+    const void *fns[] = {(const void *)k_scatter<1, 512>,  (const void *)k_scatter<2, 512>,
+                         (const void *)k_scatter<4, 512>,  (const void *)k_scatter<8, 512>,
+                         (const void *)k_scatter<1, 1024>, (const void *)k_scatter<2, 1024>,
+                         (const void *)k_scatter<4, 1024>, (const void *)k_scatter<8, 1024>};
     for (const void *fn : fns) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
@@ -842,15 +844,22 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
         case 3:
             {
                 const int tz = P->tile[2];
-                auto fn = tz <= 1 ? k_scatter<1> : tz <= 2 ? k_scatter<2>
-                                                 : tz <= 4 ? k_scatter<4> : k_scatter<8>;
+                const bool big = P->tile[0] == 1024;
+                auto fn = big ? (tz <= 1   ? k_scatter<1, 1024>
+                                 : tz <= 2 ? k_scatter<2, 1024>
+                                 : tz <= 4 ? k_scatter<4, 1024>
+                                           : k_scatter<8, 1024>)
+                              : (tz <= 1   ? k_scatter<1, 512>
+                                 : tz <= 2 ? k_scatter<2, 512>
+                                 : tz <= 4 ? k_scatter<4, 512>
+                                           : k_scatter<8, 512>);
                 hipLaunchKernelGGL(k_block_sums, dim3((unsigned)P->bblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step + 1, P->M, P->s.start, P->s.rec,
                                    P->s.bsum);
                 hipLaunchKernelGGL(k_pencil_scale, dim3((unsigned)P->tblocks), dim3(kBlock),
                                    P->bound_lds, st, P->dbox, P->nbox, P->s.step + 1, P->M,
                                    P->s.bsum, P->s.pscale);
-                hipLaunchKernelGGL(fn, dim3((unsigned)P->tblocks), dim3(kScatterBlock),
+                hipLaunchKernelGGL(fn, dim3((unsigned)P->tblocks), dim3(big ? 1024 : 512),
                                    P->lds_bytes, st, P->dbox, P->nbox, P->s.step + 1, P->M,
                                    P->s.start, P->s.rec, P->s.pscale);
             }

@@ -40,6 +40,7 @@ def _fill_level(db, slot, X, D):
     ((48, 40, 36), 1800, 2.0, (0, 16, 2), "clustered"),      # sigma = 2 dx, R_c = 6
     ((12, 13, 14), 60, 1.5, (0, 8, 8), "uniform"),           # tiny: pencils clipped to 3..4
     ((64, 24, 20), 3000, 1.5, (0, 1, 1), "uniform"),
+    ((64, 40, 24), 3000, 1.5, (1024, 32, 1), "clustered"),  # 1024-thread workgroups
 ])
 def test_scatter_matches_oracle(prec, shape, np_, sigma_dx, tile, placement):
     _cuda()
@@ -302,7 +303,7 @@ def test_tuner_picks_a_valid_tile(tmp_path):
             plan.step(n)
         plan.tune(cache)
         t = plan.get_tile()
-        assert t[0] == 0 and 1 <= t[1] <= 64 and 1 <= t[2] <= 8
+        assert t[0] in (512, 1024) and 1 <= t[1] <= 64 and 1 <= t[2] <= 8
     db2 = upload(box, w.M, erpp.F32_FAST)
     with erpp.Plan([db2], w.M, w.dt) as plan2:
         plan2.tune(cache)                       # cache hit, no timing
