@@ -2,9 +2,12 @@
 on the same arrays, compare."""
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 import oracle
+from oracle import brute
 import workloads
 
 
@@ -98,3 +101,45 @@ def sampled_parity(box, db, M, dt, steps, precision, rng, nsample=4000, wn=(24, 
     ix = (np.arange(wn[0]) + lo[0]) % box.n[0]
     fw = fg[:, iz][:, :, iy][:, :, :, ix]
     return ev, ex, rel_l2(fw, fo)
+
+
+# ------------------------------------------------ fluid-step helpers ----
+
+def grid(n, L):
+    ax = [np.arange(m) * (Li / m) for m, Li in zip(n, L)]
+    z, y, x = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return x, y, z
+
+
+def periodic_gaussian(n, L, xp, s):
+    """Normalised Gaussian of variance s^2 at xp, summed over the 27 nearest
+    periodic images (the next shell is below exp(-L^2/(8 s^2)) ~ 1e-60 here)."""
+    x, y, z = grid(n, L)
+    out = np.zeros_like(x)
+    for a in (-1, 0, 1):
+        for b in (-1, 0, 1):
+            for c in (-1, 0, 1):
+                r2 = ((x - xp[0] + a * L[0]) ** 2 + (y - xp[1] + b * L[1]) ** 2
+                      + (z - xp[2] + c * L[2]) ** 2)
+                out += np.exp(-r2 / (2 * s * s))
+    return out / (2 * math.pi * s * s) ** 1.5
+
+
+def min_image(n, L, xp):
+    x, y, z = grid(n, L)
+    r = np.stack([x - xp[0], y - xp[1], z - xp[2]])
+    for i in range(3):
+        r[i] -= L[i] * np.round(r[i] / L[i])
+    return r
+
+
+def closed_form_sum(r, D, sR, nu, dt, rho, K):
+    """Sum over the last K forcing steps of the App. E disturbance of one step,
+    the k-th one diffused k dt longer: sigma_k^2 = sigma_R^2 + 2 nu k dt."""
+    rn = np.sqrt(np.sum(r * r, axis=0))
+    m = rn > 1e-9
+    out = np.zeros_like(r)
+    for k in range(1, K + 1):
+        ss = math.sqrt(sR * sR + 2 * nu * k * dt)
+        out[:, m] += brute.green_tensor_velocity(r[:, m], D[:, None], ss, dt, rho)
+    return out, m
