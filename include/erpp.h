@@ -167,6 +167,48 @@ erpp_status erpp_stage_times(erpp_plan *plan, int64_t step0, int64_t nsteps, dou
 /* Release the plan's scratch and graph.  NULL-safe.  Synchronises the device. */
 void erpp_plan_destroy(erpp_plan *plan);
 
+/* ---------------------------------------------------------------------------
+ * Fluid step: the periodic unsteady-Stokes equation of the disturbance
+ * (Sec. 2.3, eq. velo_reg_eq) advanced over dt by the splitting of App. E:
+ *
+ *   forcing step    (eq. forcing_step)    u~ = u + dt f
+ *   diffusion step  (eq. diffusion_step)  u* = u~ convolved with g(., dt):
+ *                                         Fourier mode k times exp(-nu |k|^2 dt)
+ *   projection step                       lap(phi) = -div(u*), u = u* + grad(phi)
+ *
+ * done pseudo-spectrally with hipFFT on the grid of a box (nodes x_i = i L/N,
+ * k = 2 pi m / L).  The mean mode is kept, so rho_f * sum(u) dV grows by
+ * exactly rho_f * dt * sum(f) dV: the total impulse of Sec. 3.1.  Nyquist
+ * index of an even N: the projection's derivatives (div, grad) take that
+ * wavenumber component as zero (the grid derivative of (-1)^j vanishes at
+ * every node); the diffusion keeps the full |k|^2.  With f the
+ * forcing of erpp_scatter/erpp_step this closes the two-way coupling loop for
+ * boxes without mean shear (shear needs a deforming-frame transform, not
+ * provided).
+ * --------------------------------------------------------------------------- */
+typedef struct erpp_fluid erpp_fluid;   /* opaque: FFT plans, spectral buffer */
+
+/* Create a fluid stepper for an Nx x Ny x Nz grid of box lengths L, kinematic
+ * viscosity nu >= 0 and step dt > 0.  precision ERPP_F32_FAST: u and f float,
+ * FP32 transforms; ERPP_F64_PLAIN: double, FP64 transforms.  Allocates the
+ * spectral buffer (3 Nz Ny (Nx/2+1) complex) and the FFT plans on the current
+ * device; `stream` is the stream of later calls (may be changed per call).
+ * ERPP_EINVAL for a NULL out pointer, bad nu/dt/precision; ERPP_EGEOM for
+ * N < 1 or L <= 0; ERPP_EUNSUPPORTED beyond 4096 nodes per dimension or
+ * 3 N^3 > 2^31-1 values; ERPP_ENOMEM / ERPP_EHIP when allocation or an FFT plan
+ * fails. */
+erpp_status erpp_fluid_create(erpp_fluid **fluid, const int32_t n[3], const double L[3],
+                              double nu, double dt, erpp_precision precision, void *stream);
+
+/* One step in place: u <- P exp(nu dt lap) (u + dt f).  u, f: device
+ * [3][Nz][Ny][Nx] of the stepper's precision, caller-owned, not aliased; f is
+ * only read.  Asynchronous on `stream`. */
+erpp_status erpp_fluid_step(erpp_fluid *fluid, void *u, const void *f, void *stream);
+
+/* Release the FFT plans and the spectral buffer.  NULL-safe.  Synchronises the
+ * device. */
+void erpp_fluid_destroy(erpp_fluid *fluid);
+
 const char *erpp_status_string(erpp_status status);
 const char *erpp_last_error(void);   /* thread-local detail of the last failure */
 

@@ -20,7 +20,8 @@ F64_PLAIN, F32_FAST = 0, 1
 
 EXPORTS = ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile", "erpp_plan_tune",
            "erpp_plan_bins", "erpp_bin", "erpp_scatter", "erpp_gather", "erpp_step", "erpp_run",
-           "erpp_stage_times", "erpp_plan_destroy", "erpp_status_string", "erpp_last_error"]
+           "erpp_stage_times", "erpp_plan_destroy", "erpp_status_string", "erpp_last_error",
+           "erpp_fluid_create", "erpp_fluid_step", "erpp_fluid_destroy"]
 
 
 class ErppError(RuntimeError):
@@ -69,9 +70,15 @@ def load(path: str = LIB_PATH):
     lib.erpp_status_string.restype = C.c_char_p
     lib.erpp_last_error.argtypes = []
     lib.erpp_last_error.restype = C.c_char_p
+    lib.erpp_fluid_create.argtypes = [C.POINTER(vp), C.POINTER(i32), C.POINTER(d), d, d, C.c_int,
+                                      vp]
+    lib.erpp_fluid_step.argtypes = [vp, vp, vp, vp]
+    lib.erpp_fluid_destroy.argtypes = [vp]
+    lib.erpp_fluid_destroy.restype = None
     for name in ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile",
                  "erpp_plan_tune", "erpp_plan_bins", "erpp_bin", "erpp_scatter", "erpp_gather",
-                 "erpp_step", "erpp_run", "erpp_stage_times"]:
+                 "erpp_step", "erpp_run", "erpp_stage_times", "erpp_fluid_create",
+                 "erpp_fluid_step"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -243,3 +250,49 @@ class Plan:
     def run(self, step0: int, nsteps: int, graph: bool = True, stream=None):
         _check(self.lib.erpp_run(self.h, int(step0), int(nsteps), int(bool(graph)),
                                  _stream(stream)), "erpp_run")
+
+
+class Fluid:
+    """An erpp_fluid: the App. E unsteady-Stokes step u <- P exp(nu dt lap)(u + dt f)
+    on one periodic grid (see erpp.h)."""
+
+    def __init__(self, n, L, nu: float, dt: float, precision: int = F32_FAST, stream=None):
+        self.lib = load()
+        self.n = tuple(int(a) for a in n)
+        self.L = tuple(float(a) for a in L)
+        self.nu, self.dt, self.precision = float(nu), float(dt), int(precision)
+        h = C.c_void_p()
+        _check(self.lib.erpp_fluid_create(C.byref(h), (C.c_int32 * 3)(*self.n),
+                                          (C.c_double * 3)(*self.L), self.nu, self.dt,
+                                          self.precision, _stream(stream)), "erpp_fluid_create")
+        self.h = h
+
+    def step(self, u, f, stream=None):
+        """Advance u ([3][Nz][Ny][Nx] device tensor, updated in place) by one step
+        with forcing f (same shape and dtype)."""
+        import torch
+        want = torch.float32 if self.precision == F32_FAST else torch.float64
+        shape = (3, self.n[2], self.n[1], self.n[0])
+        for name, t in (("u", u), ("f", f)):
+            if t.dtype != want or tuple(t.shape) != shape or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous {want} tensor of shape {shape}")
+        _check(self.lib.erpp_fluid_step(self.h, C.c_void_p(u.data_ptr()),
+                                        C.c_void_p(f.data_ptr()), _stream(stream)),
+               "erpp_fluid_step")
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.erpp_fluid_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -8,11 +8,13 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liberpp.so")
-SOURCES = ["api.hip", "fast.hip", "plain.hip"]
+SOURCES = ["api.hip", "fast.hip", "plain.hip", "fluid.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(HERE, "..", "include")]
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+LIBS = ["-L" + ROCM_LIB, "-Wl,-rpath," + ROCM_LIB, "-lhipfft"]
 
 
 def build(verbose: bool = False) -> str:
@@ -26,7 +28,7 @@ def build(verbose: bool = False) -> str:
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + LIBS
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

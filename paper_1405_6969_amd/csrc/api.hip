@@ -16,7 +16,7 @@
 
 #include "erpp_internal.hpp"
 
-namespace {
+namespace erpp {
 
 thread_local std::string g_err;
 
@@ -33,6 +33,14 @@ erpp_status fail(erpp_status s, const char *fmt, ...) {
 erpp_status hip_fail(hipError_t e, const char *what) {
     return fail(ERPP_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+}  // namespace erpp
+
+namespace {
+
+using erpp::fail;
+using erpp::g_err;
+using erpp::hip_fail;
 
 #define HIP_OR_RETURN(expr)                              \
     do {                                                 \

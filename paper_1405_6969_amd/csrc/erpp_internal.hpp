@@ -114,6 +114,10 @@ struct erpp_plan {
 };
 
 namespace erpp {
+// error reporting shared by the ABI entry points: sets erpp_last_error()
+erpp_status fail(erpp_status s, const char *fmt, ...);
+erpp_status hip_fail(hipError_t e, const char *what);
+
 // kernel launchers (each returns hipSuccess or the launch error)
 hipError_t fast_stage(erpp_plan *p, int k, hipStream_t st);      // k = 0 bin .. 4 update
 hipError_t plain_stage(erpp_plan *p, int k, hipStream_t st);

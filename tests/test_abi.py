@@ -105,3 +105,40 @@ def test_null_plan_calls():
     assert lib.erpp_run(None, 0, 1, 1, None) == -1
     assert lib.erpp_plan_tune(None, None, None) == -1
     lib.erpp_plan_destroy(None)   # NULL-safe
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("null_out", -1), ("n0", -4), ("L0", -4), ("nu_neg", -1), ("dt0", -1), ("prec", -1),
+    ("n_huge", -5), ("too_many", -5),
+])
+def test_fluid_create_invalid_arguments(case, expect):
+    erpp, lib = _lib()
+    n, L, nu, dt, prec = [16, 16, 16], [1.0, 1.0, 1.0], 0.01, 1e-3, 1
+    h = C.c_void_p()
+    out = C.byref(h)
+    if case == "null_out":
+        out = None
+    elif case == "n0":
+        n[1] = 0
+    elif case == "L0":
+        L[2] = 0.0
+    elif case == "nu_neg":
+        nu = -1.0
+    elif case == "dt0":
+        dt = 0.0
+    elif case == "prec":
+        prec = 5
+    elif case == "n_huge":
+        n[0] = 5000
+    elif case == "too_many":
+        n = [1024, 1024, 1024]
+    st = lib.erpp_fluid_create(out, (C.c_int32 * 3)(*n), (C.c_double * 3)(*L), nu, dt, prec, None)
+    assert st == expect
+    assert not h.value
+    assert lib.erpp_last_error()
+
+
+def test_fluid_step_null_arguments():
+    erpp, lib = _lib()
+    assert lib.erpp_fluid_step(None, None, None, None) == -1
+    lib.erpp_fluid_destroy(None)

@@ -1,0 +1,189 @@
+"""GPU parity of the fluid step (erpp_fluid_step, App. E splitting) against the
+FP64 oracle, and the constant-force validation of Sec. 3.1 run through the C ABI
+(erpp_scatter for the regularised forcing, erpp_fluid_step for the fluid).
+
+Bars (written here): ERPP_F64_PLAIN max |u - u_oracle| <= 1e-12 max|u_oracle|;
+ERPP_F32_FAST rel-L2 <= 2e-6 and max <= 1e-5 max|u_oracle| after three steps.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import fluid as ofluid
+from helpers import closed_form_sum, min_image, rel_l2
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+erpp = pytest.importorskip("paper_1405_6969_amd")
+PRECS = [erpp.F32_FAST, erpp.F64_PLAIN]
+
+
+def _cuda():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _dtype(prec):
+    return torch.float32 if prec == erpp.F32_FAST else torch.float64
+
+
+def _round(a, prec):
+    """The values both sides consume: FP32-rounded for the FP32 path."""
+    return a.astype(np.float32).astype(np.float64) if prec == erpp.F32_FAST else a
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,L", [
+    ((12, 10, 8), (3.0, 2.5, 1.7)),            # Nyquist index in every dimension
+    ((33, 20, 17), (2.0, 1.3, 1.1)),           # odd and ragged
+    ((64, 48, 40), (6.283185307179586, 4.71238898038469, 3.9269908169872414)),
+    ((2, 16, 9), (1.0, 2.0, 1.5)),             # degenerate: x holds only the mean and Nyquist
+])
+def test_fluid_step_matches_oracle(prec, n, L):
+    _cuda()
+    rng = np.random.default_rng(sum(n))
+    nu, dt = 0.03, 0.07
+    shape = (3, n[2], n[1], n[0])
+    u = _round(rng.standard_normal(shape), prec)
+    fs = [_round(rng.standard_normal(shape), prec) for _ in range(3)]
+    ud = torch.as_tensor(u, dtype=_dtype(prec), device="cuda").contiguous()
+    with erpp.Fluid(n, L, nu, dt, precision=prec) as fl:
+        for f in fs:
+            fd = torch.as_tensor(f, dtype=_dtype(prec), device="cuda").contiguous()
+            fl.step(ud, fd)
+            u = ofluid.fluid_step(n, L, nu, dt, u, f)
+        torch.cuda.synchronize()
+    got = ud.double().cpu().numpy()
+    scale = np.max(np.abs(u))
+    if prec == erpp.F64_PLAIN:
+        assert np.max(np.abs(got - u)) <= 1e-12 * scale
+    else:
+        assert rel_l2(got, u) <= 2e-6
+        assert np.max(np.abs(got - u)) <= 1e-5 * scale
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_fluid_impulse_balance(prec):
+    """Sec. 3.1: the impulse rho_f sum(u) dV grows by rho_f dt sum(f) dV per step."""
+    _cuda()
+    n, L, rho = (40, 36, 30), (2.0, 1.8, 1.5), 1.3
+    rng = np.random.default_rng(5)
+    dV = np.prod(L) / np.prod(n)
+    shape = (3, n[2], n[1], n[0])
+    u0 = _round(rng.standard_normal(shape), prec)
+    ud = torch.as_tensor(u0, dtype=_dtype(prec), device="cuda").contiguous()
+    applied = np.zeros(3)
+    dt = 0.05
+    with erpp.Fluid(n, L, 0.02, dt, precision=prec) as fl:
+        for _ in range(6):
+            f = _round(rng.standard_normal(shape) + np.array([0.2, -0.1, 0.4])[:, None, None, None],
+                       prec)
+            applied += rho * dt * dV * f.reshape(3, -1).sum(axis=1)
+            fl.step(ud, torch.as_tensor(f, dtype=_dtype(prec), device="cuda").contiguous())
+        torch.cuda.synchronize()
+    I = ofluid.impulse(ud.double().cpu().numpy(), dV, rho)
+    want = ofluid.impulse(u0, dV, rho) + applied
+    # FP32: the transforms round the mean of a random field (sum |u| >> |sum u|)
+    tol = 1e-11 if prec == erpp.F64_PLAIN else 1e-4
+    assert np.allclose(I, want, rtol=0, atol=tol * np.max(np.abs(want)))
+
+
+def _fixed_force_run(prec, N, Lb, M, K, nu=1.0, rho=1.0, eps=0.01, offset=0.3):
+    """Constant force F = (1, 0, 0) held at a fixed point from t = 0: every ring
+    level holds x_p and D = -F, so erpp_scatter(M + s) deposits the regularised
+    force of step s; erpp_fluid_step advances the fluid.  Returns the field, the
+    force position and the oracle's run of the same steps."""
+    sR = math.sqrt(2 * nu * eps)
+    dt = eps / M
+    n, L, dx = (N,) * 3, (Lb,) * 3, Lb / N
+    xp = np.array([[N // 2 * dx + offset * dx], [N // 2 * dx], [N // 2 * dx]])
+    D = np.array([[-1.0], [0.0], [0.0]])
+    u0 = np.zeros((3, N, N, N))
+    db = erpp.device_box(n, L, xp, np.zeros((3, 1)), np.ones(1), u0, M, 1.0, rho, nu, sR,
+                         precision=prec)
+    for lvl in range(M + 1):
+        db.ring_x[lvl].copy_(torch.as_tensor(xp))
+        db.ring_d[lvl].copy_(torch.as_tensor(D, dtype=db.ring_d.dtype))
+    with erpp.Plan([db], M, dt, precision=prec) as plan, \
+            erpp.Fluid(n, L, nu, dt, precision=prec) as fl:
+        for s in range(K):
+            plan.scatter(M + s)
+            fl.step(db.u, db.f)
+        torch.cuda.synchronize()
+    return db.u.double().cpu().numpy(), xp[:, 0], D[:, 0], sR, dt, n, L
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_fixed_force_matches_oracle_and_closed_form(prec):
+    """Sec. 3.1 on a 48^3 box of side 2 pi (sigma_R / dx = 1.08, eps_R = 0.01,
+    M = 10, 50 steps): the GPU field equals the oracle's deposit + fluid steps
+    (parity bar above), the impulse is F t, and the field follows the stepped
+    App. E closed form within 3% of its peak, and beyond 6 sigma_R within twice
+    the periodic mean flow (same bounds as the oracle's own pin)."""
+    _cuda()
+    N, Lb, M, K, rho = 48, 2 * math.pi, 10, 50, 1.0
+    u, xp, D, sR, dt, n, L = _fixed_force_run(prec, N, Lb, M, K)
+    P = oracle.make_params(n, L, 1, 1.0, rho, 1.0, sR, 3.0, 0.0, M, dt)
+    f = oracle.deposit(P, xp[:, None], D[:, None])
+    f = _round(f, prec)
+    uo = np.zeros_like(f)
+    for _ in range(K):
+        uo = ofluid.fluid_step(n, L, 1.0, dt, uo, f)
+    if prec == erpp.F64_PLAIN:
+        assert np.max(np.abs(u - uo)) <= 1e-12 * np.max(np.abs(uo))
+    else:
+        assert rel_l2(u, uo) <= 2e-6
+    dx = Lb / N
+    I = ofluid.impulse(u, dx ** 3, rho)
+    print(f"impulse {I}, exact {K * dt}")
+    assert np.allclose(I, [K * dt, 0, 0], rtol=0,
+                       atol=K * dt * (1e-12 if prec == erpp.F64_PLAIN else 2e-4))
+    r = min_image(n, L, xp)
+    ref, m = closed_form_sum(r, D, sR, 1.0, dt, rho, K)
+    mean = K * dt / (rho * Lb ** 3)
+    err = np.abs(u - ref)
+    err[0] = np.abs(u[0] - ref[0] - mean)
+    rn = np.sqrt(np.sum(r * r, axis=0))
+    assert err[:, m].max() < 0.03 * np.abs(ref).max()
+    assert err[:, m & (rn > 6 * sR)].max() < 2.0 * mean
+
+
+@pytest.mark.parametrize("t_end", [0.05, 1.0])
+def test_fixed_force_velocity_profile_paper_case(t_end):
+    """The figure of Sec. 3.1: box L_B = 4 pi, eps_R = 0.01, nu = rho_f = 1
+    (sigma_R = 0.141), 90^3 nodes (sigma_R / Dx = 1.01), force (1, 0, 0); u
+    along the x axis through the force at t = 0.05 and t = 1 (FP32 path).
+    Against the stepped App. E closed form (what the scheme computes in an
+    unbounded fluid): within 3% of the peak, within twice the periodic mean flow
+    beyond 6 sigma_R.  Against eq. ref_velo_f_fixed for the regularised force,
+    u_ref(t + eps_R) - u_ref(eps_R): within 5% for 3 sigma_R <= r <= L_B / 8 (the
+    difference is the first-order time stepping, dt = eps_R / 10, and the
+    periodic images).  Impulse F t to FP32 rounding."""
+    _cuda()
+    N, Lb, M = 90, 4 * math.pi, 10
+    eps, nu, rho = 0.01, 1.0, 1.0
+    dt = eps / M
+    K = int(round(t_end / dt))
+    u, xp, D, sR, dt, n, L = _fixed_force_run(erpp.F32_FAST, N, Lb, M, K, offset=0.0)
+    dx = Lb / N
+    i0 = N // 2
+    idx = np.arange(i0 + 1, N)
+    rc = (idx - i0) * dx
+    cut = u[0, i0, i0, idx]
+    rr = np.stack([rc, 0 * rc, 0 * rc])
+    disc, _ = closed_form_sum(rr, D, sR, nu, dt, rho, K)
+    mean = K * dt / (rho * Lb ** 3)
+    e = np.abs(cut - disc[0] - mean)
+    assert e.max() < 0.03 * np.abs(disc[0]).max()
+    assert e[rc > 6 * sR].max() < 2.0 * mean
+    cont = ofluid.fixed_force_velocity(rc, t_end + eps, nu, rho) - ofluid.fixed_force_velocity(rc, eps, nu, rho)
+    sel = (rc >= 3 * sR) & (rc <= Lb / 8)
+    rel = np.abs(cut[sel] - mean - cont[sel]) / cont[sel]
+    I = ofluid.impulse(u, dx ** 3, rho)
+    print(f"t={t_end}: max rel vs ref_velo_f_fixed {rel.max():.3e}, vs stepped closed form "
+          f"{e.max() / np.abs(disc[0]).max():.3e}; impulse {I}, exact {K * dt}")
+    assert rel.max() < 0.05
+    assert np.allclose(I, [K * dt, 0, 0], rtol=0, atol=1e-3 * K * dt)
