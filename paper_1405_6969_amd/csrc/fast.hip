@@ -332,11 +332,15 @@ __global__ void __launch_bounds__(kBlock) k_block_sums(const DevBox *__restrict_
         g0[k] = start[row + Xk];
         g1[k] = start[row + Xk + 1];
     }
-    float s = 0.0f;
+    // Records within a key sit in an arbitrary order (atomic ranks), so the sum
+    // runs in FP64, exact for FP32 terms unless their exponents spread over
+    // ~29 bits, and is rounded up to FP32: the bound, and with it the
+    // fixed-point scale and the forcing, do not depend on that order.
+    double s = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-        for (int g = g0[k]; g < g1[k]; ++g) s += rec_amax(rec, g);
-    bsum[B.key_off + e] = s;
+        for (int g = g0[k]; g < g1[k]; ++g) s += (double)rec_amax(rec, g);
+    bsum[B.key_off + e] = __double2float_ru(s);
 }
 
 __global__ void __launch_bounds__(kBlock) k_pencil_scale(const DevBox *__restrict__ Bs, int nbox,
@@ -346,7 +350,7 @@ __global__ void __launch_bounds__(kBlock) k_pencil_scale(const DevBox *__restric
     if (*stepp < M) return;
     extern __shared__ float win[];              // [WZ][WY][kBoundXChunk] of bsum
     __shared__ int s_dy[256], s_dz[256];
-    __shared__ int s_ncls;
+    __shared__ int s_wcnt[kBlock / 64];
     __shared__ float s_max[kBlock / 64];
     const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_t; });
     const DevBox &B = Bs[bi];
@@ -361,20 +365,36 @@ __global__ void __launch_bounds__(kBlock) k_pencil_scale(const DevBox *__restric
     const int ny = mhi1 - mlo1 + 1, nz = mhi2 - mlo2 + 1;
     const int WY = e1 + mhi1 - mlo1, WZ = e2 + mhi2 - mlo2;
     const int tid = threadIdx.x;
-    if (tid == 0) s_ncls = 0;
-    __syncthreads();
-    for (int k = tid; k < ny * nz; k += kBlock) {
-        const int dy = mlo1 + k % ny, dz = mlo2 + k / ny;
-        const float ay = (float)(dy >= 1 ? dy - 1 : -dy) * B.dxf[1];
-        const float az = (float)(dz >= 1 ? dz - 1 : -dz) * B.dxf[2];
-        if (fmaf(ay, ay, az * az) <= B.R2f + B.guard) {
-            const int i = atomicAdd(&s_ncls, 1);
-            s_dy[i] = dy;
-            s_dz[i] = dz;
+    // reachable row classes in (dz, dy) order: a deterministic compaction
+    // (ballot ranks + wave counts), so the FP32 class sums below, the bound and
+    // the pencil's fixed-point scale do not depend on wave timing
+    int ncls = 0;
+    for (int c0 = 0; c0 < ny * nz; c0 += kBlock) {
+        const int k = c0 + tid;
+        bool reach = false;
+        if (k < ny * nz) {
+            const int dy = mlo1 + k % ny, dz = mlo2 + k / ny;
+            const float ay = (float)(dy >= 1 ? dy - 1 : -dy) * B.dxf[1];
+            const float az = (float)(dz >= 1 ? dz - 1 : -dz) * B.dxf[2];
+            reach = fmaf(ay, ay, az * az) <= B.R2f + B.guard;
         }
+        const uint64_t mask = __ballot(reach);
+        const int lane = tid & 63, w = tid >> 6;
+        if (lane == 0) s_wcnt[w] = __popcll(mask);
+        __syncthreads();
+        int before = ncls, total = ncls;
+        for (int q = 0; q < kBlock / 64; ++q) {
+            before += (q < w) ? s_wcnt[q] : 0;
+            total += s_wcnt[q];
+        }
+        if (reach) {
+            const int i = before + __popcll(mask & ((1ull << lane) - 1ull));
+            s_dy[i] = mlo1 + k % ny;
+            s_dz[i] = mlo2 + k / ny;
+        }
+        ncls = total;
+        __syncthreads();
     }
-    __syncthreads();
-    const int ncls = s_ncls;
     float bmax = 0.0f;
     for (int X0 = 0; X0 < nxb; X0 += kBoundXChunk) {
         const int nx = min(kBoundXChunk, nxb - X0);
