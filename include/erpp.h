@@ -209,6 +209,19 @@ erpp_status erpp_fluid_step(erpp_fluid *fluid, void *u, const void *f, void *str
  * device. */
 void erpp_fluid_destroy(erpp_fluid *fluid);
 
+/* Two-way coupled steps step0 .. step0+nsteps-1: each step runs stages 1-5 of
+ * every box (erpp_step), then fluids[b] advances box b's carrier in place with
+ * that step's forcing, u_b <- P exp(nu dt lap)(u_b + dt f_b), so the next step
+ * gathers the disturbed fluid.  The plan's `u` pointers are written here (the
+ * coupling stages themselves only read them).  fluids[b] must match box b: same
+ * grid and lengths, the plan's precision and dt, the box's nu (the
+ * self-disturbance removed by the update is what this fluid step makes of one
+ * forcing step, App. E), and shear = 0; otherwise ERPP_EINVAL and nothing runs.
+ * use_graph = 1 captures one coupled step in a HIP graph (recaptured when the
+ * fluids change) and replays it. */
+erpp_status erpp_run_coupled(erpp_plan *plan, erpp_fluid *const *fluids, int64_t step0,
+                             int64_t nsteps, int32_t use_graph, void *stream);
+
 const char *erpp_status_string(erpp_status status);
 const char *erpp_last_error(void);   /* thread-local detail of the last failure */
 

@@ -21,7 +21,7 @@ F64_PLAIN, F32_FAST = 0, 1
 EXPORTS = ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile", "erpp_plan_tune",
            "erpp_plan_bins", "erpp_bin", "erpp_scatter", "erpp_gather", "erpp_step", "erpp_run",
            "erpp_stage_times", "erpp_plan_destroy", "erpp_status_string", "erpp_last_error",
-           "erpp_fluid_create", "erpp_fluid_step", "erpp_fluid_destroy"]
+           "erpp_fluid_create", "erpp_fluid_step", "erpp_fluid_destroy", "erpp_run_coupled"]
 
 
 class ErppError(RuntimeError):
@@ -75,10 +75,11 @@ def load(path: str = LIB_PATH):
     lib.erpp_fluid_step.argtypes = [vp, vp, vp, vp]
     lib.erpp_fluid_destroy.argtypes = [vp]
     lib.erpp_fluid_destroy.restype = None
+    lib.erpp_run_coupled.argtypes = [vp, C.POINTER(vp), i64, i64, i32, vp]
     for name in ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile",
                  "erpp_plan_tune", "erpp_plan_bins", "erpp_bin", "erpp_scatter", "erpp_gather",
                  "erpp_step", "erpp_run", "erpp_stage_times", "erpp_fluid_create",
-                 "erpp_fluid_step"]:
+                 "erpp_fluid_step", "erpp_run_coupled"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -250,6 +251,12 @@ class Plan:
     def run(self, step0: int, nsteps: int, graph: bool = True, stream=None):
         _check(self.lib.erpp_run(self.h, int(step0), int(nsteps), int(bool(graph)),
                                  _stream(stream)), "erpp_run")
+
+    def run_coupled(self, fluids, step0: int, nsteps: int, graph: bool = True, stream=None):
+        """Two-way coupled steps: coupling step, then fluids[b] advances box b's u."""
+        arr = (C.c_void_p * len(fluids))(*[f.h.value for f in fluids])
+        _check(self.lib.erpp_run_coupled(self.h, arr, int(step0), int(nsteps), int(bool(graph)),
+                                         _stream(stream)), "erpp_run_coupled")
 
 
 class Fluid:

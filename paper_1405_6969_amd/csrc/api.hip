@@ -85,11 +85,20 @@ void free_scratch(erpp_plan *p) {
     p->dbox = nullptr;
 }
 
+void drop_coupled_graph(erpp_plan *p) {
+    if (p->cgraph_exec) (void)hipGraphExecDestroy(p->cgraph_exec);
+    if (p->cgraph) (void)hipGraphDestroy(p->cgraph);
+    p->cgraph_exec = nullptr;
+    p->cgraph = nullptr;
+    p->cfluid_ids.clear();
+}
+
 void drop_graph(erpp_plan *p) {
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     p->graph_exec = nullptr;
     p->graph = nullptr;
+    drop_coupled_graph(p);
 }
 
 template <typename T>
@@ -218,6 +227,27 @@ bool fill_box_tiles(erpp_plan *p) {
 }
 
 }  // namespace erpp
+
+namespace {
+
+// One coupled step on `st`: stages 1-5 of every box, then each box's fluid step
+// on its own u and f.  `capturing`: the plain path advances the step index
+// inside the graph (the fast path's scan does it itself).
+erpp_status coupled_step(erpp_plan *p, erpp_fluid *const *fluids, hipStream_t st, bool capturing) {
+    erpp_status s = run_stages(p, st, true);
+    if (s != ERPP_OK) return s;
+    if (capturing && p->prec == ERPP_F64_PLAIN) {
+        hipError_t e = erpp::advance_step(p, st);
+        if (e != hipSuccess) return hip_fail(e, "advance_step");
+    }
+    for (int32_t b = 0; b < p->nbox; ++b) {
+        s = erpp::fluid_launch(fluids[b], const_cast<void *>(p->boxes[b].u), p->boxes[b].f, st);
+        if (s != ERPP_OK) return s;
+    }
+    return ERPP_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -484,6 +514,63 @@ erpp_status erpp_run(erpp_plan *p, int64_t step0, int64_t nsteps, int32_t use_gr
     }
     HIP_OR_RETURN(erpp::set_step(p, step0, st));
     for (int64_t i = 0; i < nsteps; ++i) HIP_OR_RETURN(hipGraphLaunch(p->graph_exec, st));
+    return ERPP_OK;
+}
+
+erpp_status erpp_run_coupled(erpp_plan *p, erpp_fluid *const *fluids, int64_t step0,
+                             int64_t nsteps, int32_t use_graph, void *stream) {
+    if (!p) return fail(ERPP_EINVAL, "plan is NULL");
+    if (!fluids) return fail(ERPP_EINVAL, "fluids is NULL");
+    if (step0 < 0 || nsteps < 0) return fail(ERPP_EINVAL, "step0 and nsteps must be >= 0");
+    for (int32_t b = 0; b < p->nbox; ++b) {
+        if (!fluids[b]) return fail(ERPP_EINVAL, "fluids[%d] is NULL", b);
+        erpp_status s = erpp::fluid_check(fluids[b], p->boxes[b], p->dt, p->prec, b);
+        if (s != ERPP_OK) return s;
+    }
+    hipStream_t st = as_stream(stream);
+    if (!use_graph) {
+        for (int64_t i = 0; i < nsteps; ++i) {
+            HIP_OR_RETURN(erpp::set_step(p, step0 + i, st));
+            erpp_status s = coupled_step(p, fluids, st, false);
+            if (s != ERPP_OK) return s;
+        }
+        return ERPP_OK;
+    }
+    std::vector<uint64_t> ids(p->nbox);
+    for (int32_t b = 0; b < p->nbox; ++b) ids[b] = erpp::fluid_id(fluids[b]);
+    if (p->cgraph_exec && ids != p->cfluid_ids) drop_coupled_graph(p);
+    if (!p->cgraph_exec) {
+        hipStream_t cap;
+        HIP_OR_RETURN(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            (void)hipStreamDestroy(cap);
+            return hip_fail(e, "hipStreamBeginCapture");
+        }
+        erpp_status s = coupled_step(p, fluids, cap, true);
+        hipGraph_t g = nullptr;
+        hipError_t e3 = hipStreamEndCapture(cap, &g);
+        (void)hipStreamDestroy(cap);
+        if (s != ERPP_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e3 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(e3, "graph capture of the coupled step");
+        }
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        p->cgraph = g;
+        p->cgraph_exec = ex;
+        p->cfluid_ids = ids;
+    }
+    HIP_OR_RETURN(erpp::set_step(p, step0, st));
+    for (int64_t i = 0; i < nsteps; ++i) HIP_OR_RETURN(hipGraphLaunch(p->cgraph_exec, st));
     return ERPP_OK;
 }
 

@@ -111,12 +111,24 @@ struct erpp_plan {
     // graph of one step (step index read from s.step)
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    // graph of one coupled step (coupling step, then the fluid step of every box)
+    // and the identities of the fluid steppers it was captured with
+    hipGraph_t cgraph = nullptr;
+    hipGraphExec_t cgraph_exec = nullptr;
+    std::vector<uint64_t> cfluid_ids;
 };
 
 namespace erpp {
 // error reporting shared by the ABI entry points: sets erpp_last_error()
 erpp_status fail(erpp_status s, const char *fmt, ...);
 erpp_status hip_fail(hipError_t e, const char *what);
+
+// fluid stepper (fluid.hip): a unique id per created stepper, the check that it
+// fits box `ibox` of a plan, and the launches of one step on a stream
+uint64_t fluid_id(const erpp_fluid *fl);
+erpp_status fluid_check(const erpp_fluid *fl, const erpp_box &b, double dt, erpp_precision prec,
+                        int ibox);
+erpp_status fluid_launch(erpp_fluid *fl, void *u, const void *f, hipStream_t st);
 
 // kernel launchers (each returns hipSuccess or the launch error)
 hipError_t fast_stage(erpp_plan *p, int k, hipStream_t st);      // k = 0 bin .. 4 update

@@ -14,6 +14,7 @@
 #include <hipfft/hipfft.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <new>
@@ -21,6 +22,7 @@
 #include "erpp_internal.hpp"
 
 struct erpp_fluid {
+    uint64_t id;        // unique per created stepper (graph bookkeeping)
     int32_t n[3];
     double L[3];
     double nu, dt;
@@ -161,7 +163,63 @@ hipError_t launch_spectral(erpp_fluid *fl, hipStream_t st) {
     return hipGetLastError();
 }
 
+std::atomic<uint64_t> g_fluid_serial{1};
+
 }  // namespace
+
+namespace erpp {
+
+uint64_t fluid_id(const erpp_fluid *fl) { return fl->id; }
+
+erpp_status fluid_check(const erpp_fluid *fl, const erpp_box &b, double dt, erpp_precision prec,
+                        int ibox) {
+    for (int d = 0; d < 3; ++d) {
+        if (fl->n[d] != b.n[d])
+            return fail(ERPP_EINVAL, "box %d: fluid grid n[%d]=%d differs from the box's %d", ibox,
+                        d, fl->n[d], b.n[d]);
+        if (std::fabs(fl->L[d] - b.L[d]) > 1e-12 * b.L[d])
+            return fail(ERPP_EINVAL, "box %d: fluid L[%d] differs from the box's", ibox, d);
+    }
+    if (fl->prec != prec) return fail(ERPP_EINVAL, "box %d: fluid precision differs", ibox);
+    if (std::fabs(fl->dt - dt) > 1e-12 * dt)
+        return fail(ERPP_EINVAL, "box %d: fluid dt differs from the plan's", ibox);
+    // the self-disturbance removed by the update is what this fluid step makes
+    // of one forcing step (App. E), so both must use the same viscosity
+    if (std::fabs(fl->nu - b.nu) > 1e-12 * std::fabs(b.nu))
+        return fail(ERPP_EINVAL, "box %d: fluid nu differs from the box's", ibox);
+    if (b.shear != 0.0)
+        return fail(ERPP_EINVAL, "box %d: the fluid step needs shear = 0", ibox);
+    return ERPP_OK;
+}
+
+erpp_status fluid_launch(erpp_fluid *fl, void *u, const void *f, hipStream_t st) {
+    hipfftResult r = hipfftSetStream(fl->fwd, st);
+    if (r == HIPFFT_SUCCESS) r = hipfftSetStream(fl->inv, st);
+    if (r != HIPFFT_SUCCESS) return fail(ERPP_EHIP, "hipfftSetStream: %s", fft_error(r));
+    hipError_t e;
+    if (fl->prec == ERPP_F32_FAST) {
+        e = launch_force(fl, (float *)u, (const float *)f, st);
+        if (e != hipSuccess) return hip_fail(e, "k_fluid_force launch");
+        r = hipfftExecR2C(fl->fwd, (hipfftReal *)u, (hipfftComplex *)fl->spec);
+        if (r != HIPFFT_SUCCESS) return fail(ERPP_EHIP, "hipfftExecR2C: %s", fft_error(r));
+        e = launch_spectral<float>(fl, st);
+        if (e != hipSuccess) return hip_fail(e, "k_fluid_spectral launch");
+        r = hipfftExecC2R(fl->inv, (hipfftComplex *)fl->spec, (hipfftReal *)u);
+        if (r != HIPFFT_SUCCESS) return fail(ERPP_EHIP, "hipfftExecC2R: %s", fft_error(r));
+    } else {
+        e = launch_force(fl, (double *)u, (const double *)f, st);
+        if (e != hipSuccess) return hip_fail(e, "k_fluid_force launch");
+        r = hipfftExecD2Z(fl->fwd, (hipfftDoubleReal *)u, (hipfftDoubleComplex *)fl->spec);
+        if (r != HIPFFT_SUCCESS) return fail(ERPP_EHIP, "hipfftExecD2Z: %s", fft_error(r));
+        e = launch_spectral<double>(fl, st);
+        if (e != hipSuccess) return hip_fail(e, "k_fluid_spectral launch");
+        r = hipfftExecZ2D(fl->inv, (hipfftDoubleComplex *)fl->spec, (hipfftDoubleReal *)u);
+        if (r != HIPFFT_SUCCESS) return fail(ERPP_EHIP, "hipfftExecZ2D: %s", fft_error(r));
+    }
+    return ERPP_OK;
+}
+
+}  // namespace erpp
 
 extern "C" {
 
@@ -189,6 +247,7 @@ erpp_status erpp_fluid_create(erpp_fluid **out, const int32_t n[3], const double
         fl->n[d] = n[d];
         fl->L[d] = L[d];
     }
+    fl->id = g_fluid_serial.fetch_add(1);
     fl->nu = nu;
     fl->dt = dt;
     fl->prec = prec;
@@ -232,31 +291,7 @@ erpp_status erpp_fluid_step(erpp_fluid *fl, void *u, const void *f, void *stream
     if (!fl) return fail(ERPP_EINVAL, "fluid is NULL");
     if (!u || !f) return fail(ERPP_EINVAL, "u or f is NULL");
     if (u == f) return fail(ERPP_EINVAL, "u and f alias");
-    hipStream_t st = (hipStream_t)stream;
-    hipfftResult r = hipfftSetStream(fl->fwd, st);
-    if (r == HIPFFT_SUCCESS) r = hipfftSetStream(fl->inv, st);
-    if (r != HIPFFT_SUCCESS) return fail(ERPP_EHIP, "hipfftSetStream: %s", fft_error(r));
-    hipError_t e;
-    if (fl->prec == ERPP_F32_FAST) {
-        e = launch_force(fl, (float *)u, (const float *)f, st);
-        if (e != hipSuccess) return erpp::hip_fail(e, "k_fluid_force launch");
-        r = hipfftExecR2C(fl->fwd, (hipfftReal *)u, (hipfftComplex *)fl->spec);
-        if (r != HIPFFT_SUCCESS) return fail(ERPP_EHIP, "hipfftExecR2C: %s", fft_error(r));
-        e = launch_spectral<float>(fl, st);
-        if (e != hipSuccess) return erpp::hip_fail(e, "k_fluid_spectral launch");
-        r = hipfftExecC2R(fl->inv, (hipfftComplex *)fl->spec, (hipfftReal *)u);
-        if (r != HIPFFT_SUCCESS) return fail(ERPP_EHIP, "hipfftExecC2R: %s", fft_error(r));
-    } else {
-        e = launch_force(fl, (double *)u, (const double *)f, st);
-        if (e != hipSuccess) return erpp::hip_fail(e, "k_fluid_force launch");
-        r = hipfftExecD2Z(fl->fwd, (hipfftDoubleReal *)u, (hipfftDoubleComplex *)fl->spec);
-        if (r != HIPFFT_SUCCESS) return fail(ERPP_EHIP, "hipfftExecD2Z: %s", fft_error(r));
-        e = launch_spectral<double>(fl, st);
-        if (e != hipSuccess) return erpp::hip_fail(e, "k_fluid_spectral launch");
-        r = hipfftExecZ2D(fl->inv, (hipfftDoubleComplex *)fl->spec, (hipfftDoubleReal *)u);
-        if (r != HIPFFT_SUCCESS) return fail(ERPP_EHIP, "hipfftExecZ2D: %s", fft_error(r));
-    }
-    return ERPP_OK;
+    return erpp::fluid_launch(fl, u, f, (hipStream_t)stream);
 }
 
 void erpp_fluid_destroy(erpp_fluid *fl) {
