@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-steps", type=int, default=10)
+    ap.add_argument("--no-coupled", action="store_true",
+                    help="skip the two-way coupled run (coupling step + fluid step)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (the reference kernel "
                          "for scaling HBM counter readings)")
@@ -240,6 +242,12 @@ def main():
         log(f"[bench] oracle {cpu}")
 
     plan.close()
+    coupled = None
+    if not args.no_coupled and len(boxes) == 1:
+        del dbs
+        torch.cuda.empty_cache()
+        coupled = bench_coupled(boxes[0], w, tile, min(K, 100), erpp, torch)
+        log(f"[bench] coupled {coupled}")
     if args.copy_calibration > 0:
         nel = args.copy_calibration * (1 << 20) // 4
         src = torch.ones(nel, dtype=torch.float32, device="cuda")
@@ -265,8 +273,56 @@ def main():
         "fp64_plain": plain,
         "accuracy": accuracy,
         "cpu_baseline": cpu,
+        "coupled": coupled,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_coupled(box, w, tile, K, erpp, torch):
+    """Two-way coupling on the same grid and particles without the mean shear
+    (the fluid step is for periodic boxes at rest): each step is the coupling
+    step followed by the App. E fluid step (hipFFT), replayed as one graph.
+    Also times the fluid step alone; its algorithmic traffic is u and f read
+    and u written, 36 B per node in FP32."""
+    M, dt, s = w.M, w.dt, box.spec
+    v = box.v.copy()
+    if s.shear != 0.0:
+        v[0] -= s.shear * (box.x[1] - 0.5 * box.L[1])
+    db = erpp.device_box(box.n, box.L, box.x, v, box.tau, box.u.astype(np.float32), M, box.m_p,
+                         s.rho_f, s.nu, box.sigma, s.cutoff, 0.0, precision=erpp.F32_FAST)
+    plan = erpp.Plan([db], M, dt, precision=erpp.F32_FAST)
+    plan.set_tile(tile)
+    fl = erpp.Fluid(box.n, box.L, s.nu, dt, precision=erpp.F32_FAST)
+    warm = M + 4
+    plan.run_coupled([fl], 0, warm, graph=True)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    plan.run_coupled([fl], warm, K, graph=True)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / K
+    # the fluid step alone, on a copy of the field with the last forcing
+    u2 = db.u.clone()
+    nf = 20
+    a.record()
+    for _ in range(nf):
+        fl.step(u2, db.f)
+    b.record()
+    torch.cuda.synchronize()
+    fms = a.elapsed_time(b) / nf
+    nodes = int(np.prod(box.n))
+    fbytes = 36 * nodes
+    plan.close()
+    fl.close()
+    del db, u2
+    torch.cuda.empty_cache()
+    return {"workload": f"{w.name} without mean shear", "steps": K,
+            "ms_per_step": round(ms, 4), "value": round(box.np_ / (ms * 1e-3), 1),
+            "unit": "particle-steps/s",
+            "fluid_step": {"us": round(fms * 1e3, 1), "grid": list(box.n),
+                           "algorithmic_bytes": fbytes,
+                           "achieved_gbs": round(fbytes / (fms * 1e-3) / 1e9, 1)}}
 
 
 def check_accuracy(box, db, w, steps_done):
