@@ -35,7 +35,8 @@ class Params(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("L", C.c_double * 3), ("np", C.c_int64),
                 ("m_p", C.c_double), ("rho_f", C.c_double), ("nu", C.c_double),
                 ("sigma", C.c_double), ("cutoff", C.c_double), ("shear", C.c_double),
-                ("M", C.c_int32), ("dt", C.c_double), ("self_correction", C.c_int32)]
+                ("M", C.c_int32), ("dt", C.c_double), ("self_correction", C.c_int32),
+                ("g", C.c_double * 3)]
 
 
 _lib = None
@@ -73,7 +74,7 @@ def _f64(a):
 
 
 def make_params(n, L, np_, m_p, rho_f, nu, sigma, cutoff=3.0, shear=0.0, M=1,
-                dt=1e-3, self_correction=1) -> Params:
+                dt=1e-3, self_correction=1, g=(0.0, 0.0, 0.0)) -> Params:
     P = Params()
     P.n = (C.c_int32 * 3)(*[int(v) for v in n])
     P.L = (C.c_double * 3)(*[float(v) for v in L])
@@ -81,6 +82,7 @@ def make_params(n, L, np_, m_p, rho_f, nu, sigma, cutoff=3.0, shear=0.0, M=1,
     P.m_p, P.rho_f, P.nu, P.sigma = float(m_p), float(rho_f), float(nu), float(sigma)
     P.cutoff, P.shear = float(cutoff), float(shear)
     P.M, P.dt, P.self_correction = int(M), float(dt), int(self_correction)
+    P.g = (C.c_double * 3)(*[float(a) for a in g])
     for d in range(3):
         dxd = P.L[d] / P.n[d]
         R = int(np.ceil(P.cutoff * P.sigma / dxd))

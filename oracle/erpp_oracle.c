@@ -370,7 +370,12 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
                 if (dout) dout[d * np + p] = D[d];
                 xn[d] = x[d * np + p] + P->dt * v[d * np + p];
             }
-            for (d = 0; d < 3; ++d) v[d * np + p] += P->dt * D[d] / P->m_p;
+            /* eq. particle_motion: m_p dv/dt = D + (m_p - m_f) g; the body
+               force is not part of D, so the fluid never receives it */
+            for (d = 0; d < 3; ++d) {
+                v[d * np + p] += P->dt * D[d] / P->m_p;
+                v[d * np + p] += P->dt * P->g[d];
+            }
             for (d = 0; d < 3; ++d) {
                 double L = P->L[d];
                 double w = xn[d] - L * floor(xn[d] / L);

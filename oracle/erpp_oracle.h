@@ -36,6 +36,7 @@ typedef struct {
     int32_t M;           /* delay eps_R = M dt, in steps (>= 1) */
     double  dt;          /* time step */
     int32_t self_correction; /* 1: remove the closed-form self disturbance */
+    double  g[3];        /* body acceleration of the particles, (m_p - m_f) g / m_p */
 } oracle_params;
 
 /* Cell key of each position and a stable counting sort by key.

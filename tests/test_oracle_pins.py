@@ -346,6 +346,37 @@ def test_p10_update_geometric_series():
     assert np.max(np.abs(dxw)) < 1e-12
 
 
+def test_p10g_body_force_geometric_series():
+    """With a body acceleration g_b (eq. particle_motion: (m_p - m_f) g / m_p)
+    explicit Euler relaxes to w = u0 + tau g_b: v^n = w + (v0 - w) q^n,
+    x^n = x0 + n dt w + tau (v0 - w)(1 - q^n).  The drag handed to the fluid is
+    the hydrodynamic force alone, m_p (u0 - v^n)/tau, which tends to -m_p g_b
+    (eq. drag_coupled: at terminal velocity the drag balances gravity)."""
+    u0 = np.array([0.3, -0.2, 0.1])
+    gb = np.array([-0.9, 0.4, 2.0])
+    dt, tau, n, M = 1e-3, 0.05, 800, 3
+    box = workloads.tiny_box(61, n=(16, 16, 16), np_=8, carrier="zero", tau=(tau,))
+    u = np.zeros_like(box.u) + u0[:, None, None, None]
+    P = _params(box, M=M, dt=dt, s=0)
+    P.g = (type(P.g))(*gb)
+    run = oracle.Run(P, u, box.x, box.v, box.tau)
+    x0, v0 = box.x.copy(), box.v.copy()
+    for _ in range(n - 1):
+        run.step(want_f=False)
+    v_before = run.v.copy()
+    _, D = run.step(want_f=False)
+    tau32 = float(np.float32(tau))
+    q = 1 - dt / tau32
+    w = (u0 + tau32 * gb)[:, None]
+    assert np.allclose(run.v, w + (v0 - w) * q ** n, rtol=1e-12, atol=1e-13)
+    x_ref = x0 + n * dt * w + tau32 * (v0 - w) * (1 - q ** n)
+    dxw = run.x - x_ref
+    dxw -= box.L[0] * np.round(dxw / box.L[0])
+    assert np.max(np.abs(dxw)) < 1e-12
+    assert np.allclose(D, box.m_p * (u0[:, None] - v_before) / tau32, rtol=1e-13, atol=0)
+    assert np.allclose(D, -box.m_p * gb[:, None], rtol=1e-5)   # q^n ~ 1e-7
+
+
 def test_p10_continuum_limit_uncoupled_solution():
     """As dt -> 0 the discrete relaxation converges to the paper's one-way
     solution v = v_t (1 - e^{-t/tau_p}) (eq. uncoupled_solution), here for a
