@@ -117,6 +117,15 @@ erpp_status erpp_plan_create(erpp_plan **plan, const erpp_box *boxes, int32_t nb
 erpp_status erpp_plan_set_tile(erpp_plan *plan, const int32_t tile[3]);
 erpp_status erpp_plan_get_tile(const erpp_plan *plan, int32_t tile[3]);
 
+/* Body acceleration of the particles of box `ibox`, (m_p - m_f) g / m_p
+ * (Sec. 2.5, eq. particle_motion: gravity acts on the particle minus its
+ * displaced fluid mass).  It enters the velocity update only,
+ * v^{n+1} = v^n + dt D^n/m_p + dt g_b; the fluid receives the hydrodynamic drag
+ * D alone.  Default 0.  Applies to later steps, also to captured graphs (the
+ * value lives in the plan's device copy of the box).  Synchronises the device.
+ * ERPP_EINVAL for a bad plan or index or a non-finite component. */
+erpp_status erpp_plan_set_body_force(erpp_plan *plan, int32_t ibox, const double g[3]);
+
 /* Autotuner (ERPP_F32_FAST): times every candidate pencil shape on the plan's own
  * boxes (scatter of the current ring contents, which are only read) and keeps
  * the fastest.  With cache_path != NULL the choice is read from / appended to

@@ -21,7 +21,8 @@ F64_PLAIN, F32_FAST = 0, 1
 EXPORTS = ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile", "erpp_plan_tune",
            "erpp_plan_bins", "erpp_bin", "erpp_scatter", "erpp_gather", "erpp_step", "erpp_run",
            "erpp_stage_times", "erpp_plan_destroy", "erpp_status_string", "erpp_last_error",
-           "erpp_fluid_create", "erpp_fluid_step", "erpp_fluid_destroy", "erpp_run_coupled"]
+           "erpp_fluid_create", "erpp_fluid_step", "erpp_fluid_destroy", "erpp_run_coupled",
+           "erpp_plan_set_body_force"]
 
 
 class ErppError(RuntimeError):
@@ -76,10 +77,11 @@ def load(path: str = LIB_PATH):
     lib.erpp_fluid_destroy.argtypes = [vp]
     lib.erpp_fluid_destroy.restype = None
     lib.erpp_run_coupled.argtypes = [vp, C.POINTER(vp), i64, i64, i32, vp]
+    lib.erpp_plan_set_body_force.argtypes = [vp, i32, C.POINTER(d)]
     for name in ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile",
                  "erpp_plan_tune", "erpp_plan_bins", "erpp_bin", "erpp_scatter", "erpp_gather",
                  "erpp_step", "erpp_run", "erpp_stage_times", "erpp_fluid_create",
-                 "erpp_fluid_step", "erpp_run_coupled"]:
+                 "erpp_fluid_step", "erpp_run_coupled", "erpp_plan_set_body_force"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -194,6 +196,12 @@ class Plan:
     def set_tile(self, tile):
         t = (C.c_int32 * 3)(*tile)
         _check(self.lib.erpp_plan_set_tile(self.h, t), "erpp_plan_set_tile")
+
+    def set_body_force(self, ibox: int, g):
+        """Body acceleration (m_p - m_f) g / m_p of the particles of box ibox."""
+        _check(self.lib.erpp_plan_set_body_force(self.h, int(ibox),
+                                                 (C.c_double * 3)(*[float(a) for a in g])),
+               "erpp_plan_set_body_force")
 
     def get_tile(self):
         t = (C.c_int32 * 3)()

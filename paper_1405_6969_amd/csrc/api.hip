@@ -417,6 +417,19 @@ erpp_status erpp_plan_set_tile(erpp_plan *p, const int32_t tile[3]) {
     return upload_boxes(p);
 }
 
+erpp_status erpp_plan_set_body_force(erpp_plan *p, int32_t ibox, const double g[3]) {
+    if (!p) return fail(ERPP_EINVAL, "plan is NULL");
+    if (ibox < 0 || ibox >= p->nbox) return fail(ERPP_EINVAL, "ibox %d out of range", ibox);
+    if (!g) return fail(ERPP_EINVAL, "g is NULL");
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(g[d])) return fail(ERPP_EINVAL, "g[%d] is not finite", d);
+    for (int d = 0; d < 3; ++d) p->hbox[ibox].gb[d] = g[d];
+    HIP_OR_RETURN(hipDeviceSynchronize());
+    HIP_OR_RETURN(hipMemcpy(p->dbox + ibox, &p->hbox[ibox], sizeof(erpp::DevBox),
+                            hipMemcpyHostToDevice));
+    return ERPP_OK;
+}
+
 erpp_status erpp_plan_get_tile(const erpp_plan *p, int32_t tile[3]) {
     if (!p || !tile) return fail(ERPP_EINVAL, "NULL argument");
     for (int d = 0; d < 3; ++d) tile[d] = p->tile[d];

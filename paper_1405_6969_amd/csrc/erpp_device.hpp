@@ -251,6 +251,7 @@ __device__ __forceinline__ void update_particle(const DevBox &B, int64_t p, doub
         if (hdD) hdD[d * np + p] = D[d];
         if (hdF) hdF[d * np + p] = (float)D[d];
         vn[d] += dt * D[d] / B.m_p;
+        vn[d] += dt * B.gb[d];
     }
     for (int d = 0; d < 3; ++d) {
         double L = B.L[d];
