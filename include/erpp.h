@@ -61,7 +61,9 @@ typedef enum {
     ERPP_ENOMEM = -2,       /* device allocation of plan scratch failed           */
     ERPP_EHIP = -3,         /* a HIP runtime call failed                          */
     ERPP_EGEOM = -4,        /* grid too small for the stencil (N < 2 R_c + 2),
-                               L <= 0, sigma <= 0 or cutoff <= 0                  */
+                               L <= 0, sigma <= 0 or cutoff <= 0, or a sphere of
+                               radius cutoff*sigma that can miss every node
+                               (cutoff*sigma < half the cell diagonal)            */
     ERPP_EUNSUPPORTED = -5  /* outside the library's limits (a dimension > 2048 in
                                x/y or > 1024 in z, more than 2^31-1 particles or
                                nodes per box)                                     */

@@ -88,6 +88,10 @@ def make_params(n, L, np_, m_p, rho_f, nu, sigma, cutoff=3.0, shear=0.0, M=1,
         R = int(np.ceil(P.cutoff * P.sigma / dxd))
         if P.n[d] < 2 * R + 2:
             raise ValueError(f"grid too small: N[{d}]={P.n[d]} < 2*{R}+2")
+    rc = P.cutoff * P.sigma
+    if rc * rc < 0.25 * sum((P.L[d] / P.n[d]) ** 2 for d in range(3)):
+        raise ValueError("cutoff * sigma below half the cell diagonal: a sphere can miss "
+                         "every node and the normalisation vanishes")
     if P.M < 1:
         raise ValueError("M must be >= 1")
     return P

@@ -316,6 +316,10 @@ erpp_status erpp_plan_create(erpp_plan **out, const erpp_box *boxes, int32_t nbo
                 return fail(ERPP_EUNSUPPORTED, "box %d: stencil of %d nodes in dim %d (> 16)", b,
                             B.mhi[d] - B.mlo[d] + 1, d);
         }
+        // every position must have a node inside its sphere (the farthest point
+        // from all nodes is a cell centre), or the lattice normalisation is 0
+        if (rc * rc < 0.25 * (B.dx[0] * B.dx[0] + B.dx[1] * B.dx[1] + B.dx[2] * B.dx[2]))
+            return fail(ERPP_EGEOM, "box %d: cutoff * sigma is below half the cell diagonal", b);
         if (prec == ERPP_F32_FAST && (X.n[0] > 2048 || X.n[1] > 2048 || X.n[2] > 1024))
             return fail(ERPP_EUNSUPPORTED, "box %d: grid beyond 2048 x 2048 x 1024", b);
         B.np = X.np;

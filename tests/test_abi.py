@@ -57,7 +57,7 @@ def _create(lib, boxes, nbox=None, M=4, dt=1e-3, prec=1, s=1):
 @pytest.mark.parametrize("case,expect", [
     ("nbox0", -1), ("M0", -1), ("dt0", -1), ("prec", -1), ("selfc", -1), ("np_neg", -1),
     ("null_x", -1), ("grid_small", -4), ("L0", -4), ("sigma0", -4), ("grid_huge", -5),
-    ("stencil_wide", -5), ("mass0", -1),
+    ("stencil_wide", -5), ("mass0", -1), ("sigma_tiny", -4),
 ])
 def test_invalid_arguments_return_status(case, expect):
     erpp, lib = _lib()
@@ -84,6 +84,8 @@ def test_invalid_arguments_return_status(case, expect):
         b.L = (C.c_double * 3)(0.0, 1.0, 1.0)
     elif case == "sigma0":
         b.sigma = 0.0
+    elif case == "sigma_tiny":
+        b.sigma = 0.28 * 6.283185307179586 / 32     # 3 sigma < half the cell diagonal
     elif case == "grid_huge":
         b = _box(erpp, n=(4096, 32, 32), L=(4096 * 0.19634954084936207, 6.283185307179586,
                                             6.283185307179586), sigma=1.5 * 0.19634954084936207)

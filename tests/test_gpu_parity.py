@@ -41,6 +41,7 @@ def _fill_level(db, slot, X, D):
     ((12, 13, 14), 60, 1.5, (0, 8, 8), "uniform"),           # tiny: pencils clipped to 3..4
     ((64, 24, 20), 3000, 1.5, (0, 1, 1), "uniform"),
     ((64, 40, 24), 3000, 1.5, (1024, 32, 1), "clustered"),  # 1024-thread workgroups
+    ((20, 18, 16), 300, 0.3, (0, 4, 4), "uniform"),          # unresolved: 3 sigma < dx
 ])
 def test_scatter_matches_oracle(prec, shape, np_, sigma_dx, tile, placement):
     _cuda()
