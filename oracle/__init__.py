@@ -36,7 +36,7 @@ class Params(C.Structure):
                 ("m_p", C.c_double), ("rho_f", C.c_double), ("nu", C.c_double),
                 ("sigma", C.c_double), ("cutoff", C.c_double), ("shear", C.c_double),
                 ("M", C.c_int32), ("dt", C.c_double), ("self_correction", C.c_int32),
-                ("g", C.c_double * 3)]
+                ("g", C.c_double * 3), ("integrator", C.c_int32)]
 
 
 _lib = None
@@ -74,7 +74,7 @@ def _f64(a):
 
 
 def make_params(n, L, np_, m_p, rho_f, nu, sigma, cutoff=3.0, shear=0.0, M=1,
-                dt=1e-3, self_correction=1, g=(0.0, 0.0, 0.0)) -> Params:
+                dt=1e-3, self_correction=1, g=(0.0, 0.0, 0.0), integrator=0) -> Params:
     P = Params()
     P.n = (C.c_int32 * 3)(*[int(v) for v in n])
     P.L = (C.c_double * 3)(*[float(v) for v in L])
@@ -83,6 +83,7 @@ def make_params(n, L, np_, m_p, rho_f, nu, sigma, cutoff=3.0, shear=0.0, M=1,
     P.cutoff, P.shear = float(cutoff), float(shear)
     P.M, P.dt, P.self_correction = int(M), float(dt), int(self_correction)
     P.g = (C.c_double * 3)(*[float(a) for a in g])
+    P.integrator = int(integrator)
     for d in range(3):
         dxd = P.L[d] / P.n[d]
         R = int(np.ceil(P.cutoff * P.sigma / dxd))

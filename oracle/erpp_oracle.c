@@ -360,21 +360,42 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
             double D[3], xn[3];
             int d;
             int64_t k;
-            for (d = 0; d < 3; ++d) {
-                double ut = up[d * np + p] - vs[d * np + p];
-                D[d] = P->m_p * (ut - v[d * np + p]) / t;
-            }
-            for (d = 0; d < 3; ++d) {
-                hx[d * np + p] = x[d * np + p];
-                hd[d * np + p] = D[d];
-                if (dout) dout[d * np + p] = D[d];
-                xn[d] = x[d * np + p] + P->dt * v[d * np + p];
-            }
-            /* eq. particle_motion: m_p dv/dt = D + (m_p - m_f) g; the body
-               force is not part of D, so the fluid never receives it */
-            for (d = 0; d < 3; ++d) {
-                v[d * np + p] += P->dt * D[d] / P->m_p;
-                v[d * np + p] += P->dt * P->g[d];
+            if (P->integrator == 0) {
+                for (d = 0; d < 3; ++d) {
+                    double ut = up[d * np + p] - vs[d * np + p];
+                    D[d] = P->m_p * (ut - v[d * np + p]) / t;
+                }
+                for (d = 0; d < 3; ++d) {
+                    hx[d * np + p] = x[d * np + p];
+                    hd[d * np + p] = D[d];
+                    if (dout) dout[d * np + p] = D[d];
+                    xn[d] = x[d * np + p] + P->dt * v[d * np + p];
+                }
+                /* eq. particle_motion: m_p dv/dt = D + (m_p - m_f) g; the body
+                   force is not part of D, so the fluid never receives it */
+                for (d = 0; d < 3; ++d) {
+                    v[d * np + p] += P->dt * D[d] / P->m_p;
+                    v[d * np + p] += P->dt * P->g[d];
+                }
+            } else {
+                /* dv/dt = (u~ - v)/tau + g with u~ held over the step has the
+                   solution v(s) = w + (v^n - w) exp(-s/tau), w = u~ + tau g;
+                   x advances by its integral; the fluid receives the
+                   momentum the drag exchanged, divided by dt */
+                double E = exp(-P->dt / t);
+                double a = -expm1(-P->dt / t);   /* 1 - E without cancellation */
+                for (d = 0; d < 3; ++d) {
+                    double ut = up[d * np + p] - vs[d * np + p];
+                    double v0 = v[d * np + p];
+                    double w = ut + t * P->g[d];
+                    double v1 = w + (v0 - w) * E;
+                    hx[d * np + p] = x[d * np + p];
+                    xn[d] = x[d * np + p] + P->dt * w + t * (v0 - w) * a;
+                    D[d] = P->m_p * (v1 - v0) / P->dt - P->m_p * P->g[d];
+                    hd[d * np + p] = D[d];
+                    if (dout) dout[d * np + p] = D[d];
+                    v[d * np + p] = v1;
+                }
             }
             for (d = 0; d < 3; ++d) {
                 double L = P->L[d];

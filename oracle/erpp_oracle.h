@@ -37,6 +37,7 @@ typedef struct {
     double  dt;          /* time step */
     int32_t self_correction; /* 1: remove the closed-form self disturbance */
     double  g[3];        /* body acceleration of the particles, (m_p - m_f) g / m_p */
+    int32_t integrator;  /* 0 explicit Euler, 1 exact linear drag over the step */
 } oracle_params;
 
 /* Cell key of each position and a stable counting sort by key.

@@ -377,6 +377,42 @@ def test_p10g_body_force_geometric_series():
     assert np.allclose(D, -box.m_p * gb[:, None], rtol=1e-5)   # q^n ~ 1e-7
 
 
+@pytest.mark.parametrize("dt_over_tau", [0.02, 3.0])
+def test_p10e_exponential_integrator_is_exact_for_a_uniform_carrier(dt_over_tau):
+    """With u~ uniform the exponential integrator reproduces the continuous
+    solution of m_p dv/dt = m_p (u0 - v)/tau + m_p g_b at every step
+    (eq. uncoupled_solution with an initial slip): v = w + (v0 - w) e^{-t/tau},
+    x = x0 + w t + tau (v0 - w)(1 - e^{-t/tau}), w = u0 + tau g_b, also for
+    dt = 3 tau where explicit Euler diverges.  The drag handed to the fluid is
+    the momentum the drag exchanged over the step divided by dt."""
+    u0 = np.array([0.3, -0.2, 0.1])
+    gb = np.array([-0.9, 0.4, 2.0])
+    tau = 0.05
+    tau32 = float(np.float32(tau))
+    dt = dt_over_tau * tau32
+    n = 30
+    box = workloads.tiny_box(61, n=(16, 16, 16), np_=8, carrier="zero", tau=(tau,))
+    u = np.zeros_like(box.u) + u0[:, None, None, None]
+    P = _params(box, M=3, dt=dt, s=0)
+    P.g = (type(P.g))(*gb)
+    P.integrator = 1
+    run = oracle.Run(P, u, box.x, box.v, box.tau)
+    x0, v0 = box.x.copy(), box.v.copy()
+    for _ in range(n - 1):
+        run.step(want_f=False)
+    vb = run.v.copy()
+    _, D = run.step(want_f=False)
+    t = n * dt
+    w = (u0 + tau32 * gb)[:, None]
+    assert np.allclose(run.v, w + (v0 - w) * math.exp(-t / tau32), rtol=1e-12, atol=1e-13)
+    x_ref = x0 + w * t + tau32 * (v0 - w) * (1 - math.exp(-t / tau32))
+    dxw = run.x - x_ref
+    dxw -= box.L[0] * np.round(dxw / box.L[0])
+    assert np.max(np.abs(dxw)) < 1e-12
+    assert np.allclose(D * dt, box.m_p * (run.v - vb) - box.m_p * gb[:, None] * dt,
+                       rtol=0, atol=1e-14)
+
+
 def test_p10_continuum_limit_uncoupled_solution():
     """As dt -> 0 the discrete relaxation converges to the paper's one-way
     solution v = v_t (1 - e^{-t/tau_p}) (eq. uncoupled_solution), here for a
