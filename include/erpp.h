@@ -96,6 +96,19 @@ typedef struct {
                                particle crossing y = 0 / Ly gets v_x -/+= S Ly     */
 } erpp_box;
 
+typedef enum {
+    ERPP_EULER = 0,         /* explicit Euler (Sec. 2.5): D^n = m_p (u~ - v^n)/tau_p,
+                               v^{n+1} = v^n + dt D^n/m_p + dt g_b,
+                               x^{n+1} = x^n + dt v^n                              */
+    ERPP_EXPONENTIAL = 1    /* the linear drag ODE solved exactly over the step with
+                               u~ frozen: w = u~ + tau_p g_b,
+                               v^{n+1} = w + (v^n - w) e^{-dt/tau_p},
+                               x^{n+1} = x^n + dt w + tau_p (v^n - w)(1 - e^{-dt/tau_p});
+                               drag handed to the fluid: the step average
+                               m_p (v^{n+1} - v^n)/dt - m_p g_b.  Stable for any
+                               dt/tau_p                                            */
+} erpp_integrator;
+
 typedef struct erpp_plan erpp_plan;   /* opaque: copies of the boxes, scratch,
                                          tile shape, captured graph            */
 
@@ -127,6 +140,13 @@ erpp_status erpp_plan_get_tile(const erpp_plan *plan, int32_t tile[3]);
  * value lives in the plan's device copy of the box).  Synchronises the device.
  * ERPP_EINVAL for a bad plan or index or a non-finite component. */
 erpp_status erpp_plan_set_body_force(erpp_plan *plan, int32_t ibox, const double g[3]);
+
+/* Particle integrator of every box (default ERPP_EULER).  The self-disturbance
+ * removed from u~ is the same App. E closed form for both (the fluid receives
+ * one forcing step of the handed-over drag either way).  Applies to later
+ * steps and to captured graphs.  Synchronises the device.  ERPP_EINVAL for a
+ * bad plan or kind. */
+erpp_status erpp_plan_set_integrator(erpp_plan *plan, erpp_integrator kind);
 
 /* Autotuner (ERPP_F32_FAST): times every candidate pencil shape on the plan's own
  * boxes (scatter of the current ring contents, which are only read) and keeps

@@ -17,12 +17,13 @@ LIB_PATH = os.path.join(_HERE, "liberpp.so")
 
 ERPP_OK, ERPP_EINVAL, ERPP_ENOMEM, ERPP_EHIP, ERPP_EGEOM, ERPP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 F64_PLAIN, F32_FAST = 0, 1
+EULER, EXPONENTIAL = 0, 1
 
 EXPORTS = ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile", "erpp_plan_tune",
            "erpp_plan_bins", "erpp_bin", "erpp_scatter", "erpp_gather", "erpp_step", "erpp_run",
            "erpp_stage_times", "erpp_plan_destroy", "erpp_status_string", "erpp_last_error",
            "erpp_fluid_create", "erpp_fluid_step", "erpp_fluid_destroy", "erpp_run_coupled",
-           "erpp_plan_set_body_force"]
+           "erpp_plan_set_body_force", "erpp_plan_set_integrator"]
 
 
 class ErppError(RuntimeError):
@@ -78,10 +79,12 @@ def load(path: str = LIB_PATH):
     lib.erpp_fluid_destroy.restype = None
     lib.erpp_run_coupled.argtypes = [vp, C.POINTER(vp), i64, i64, i32, vp]
     lib.erpp_plan_set_body_force.argtypes = [vp, i32, C.POINTER(d)]
+    lib.erpp_plan_set_integrator.argtypes = [vp, C.c_int]
     for name in ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile",
                  "erpp_plan_tune", "erpp_plan_bins", "erpp_bin", "erpp_scatter", "erpp_gather",
                  "erpp_step", "erpp_run", "erpp_stage_times", "erpp_fluid_create",
-                 "erpp_fluid_step", "erpp_run_coupled", "erpp_plan_set_body_force"]:
+                 "erpp_fluid_step", "erpp_run_coupled", "erpp_plan_set_body_force",
+                 "erpp_plan_set_integrator"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -202,6 +205,10 @@ class Plan:
         _check(self.lib.erpp_plan_set_body_force(self.h, int(ibox),
                                                  (C.c_double * 3)(*[float(a) for a in g])),
                "erpp_plan_set_body_force")
+
+    def set_integrator(self, kind: int):
+        """EULER (explicit Euler) or EXPONENTIAL (exact linear drag over the step)."""
+        _check(self.lib.erpp_plan_set_integrator(self.h, int(kind)), "erpp_plan_set_integrator")
 
     def get_tile(self):
         t = (C.c_int32 * 3)()

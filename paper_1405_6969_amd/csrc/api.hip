@@ -434,6 +434,17 @@ erpp_status erpp_plan_set_body_force(erpp_plan *p, int32_t ibox, const double g[
     return ERPP_OK;
 }
 
+erpp_status erpp_plan_set_integrator(erpp_plan *p, erpp_integrator kind) {
+    if (!p) return fail(ERPP_EINVAL, "plan is NULL");
+    if (kind != ERPP_EULER && kind != ERPP_EXPONENTIAL)
+        return fail(ERPP_EINVAL, "unknown integrator %d", (int)kind);
+    for (auto &B : p->hbox) B.integ = (int32_t)kind;
+    HIP_OR_RETURN(hipDeviceSynchronize());
+    HIP_OR_RETURN(hipMemcpy(p->dbox, p->hbox.data(), sizeof(erpp::DevBox) * p->hbox.size(),
+                            hipMemcpyHostToDevice));
+    return ERPP_OK;
+}
+
 erpp_status erpp_plan_get_tile(const erpp_plan *p, int32_t tile[3]) {
     if (!p || !tile) return fail(ERPP_EINVAL, "NULL argument");
     for (int d = 0; d < 3; ++d) tile[d] = p->tile[d];

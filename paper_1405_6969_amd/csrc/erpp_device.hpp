@@ -239,19 +239,37 @@ __device__ __forceinline__ void update_particle(const DevBox &B, int64_t p, doub
     const int64_t np = B.np;
     double t = (double)B.tau[p];
     double D[3], xn[3], vn[3];
-    for (int d = 0; d < 3; ++d) {
-        double ut = up[d] - vs[d];
-        double vd = B.v[d * np + p];
-        D[d] = B.m_p * (ut - vd) / t;
-        xn[d] = xp[d] + dt * vd;
-        vn[d] = vd;
+    if (B.integ == 0) {
+        // explicit Euler: drag at (x^n, v^n), positions with the old velocity
+        for (int d = 0; d < 3; ++d) {
+            double ut = up[d] - vs[d];
+            double vd = B.v[d * np + p];
+            D[d] = B.m_p * (ut - vd) / t;
+            xn[d] = xp[d] + dt * vd;
+            vn[d] = vd;
+        }
+        for (int d = 0; d < 3; ++d) {
+            vn[d] += dt * D[d] / B.m_p;
+            vn[d] += dt * B.gb[d];
+        }
+    } else {
+        // exponential integrator: dv/dt = (u~ - v)/tau + g_b solved exactly over
+        // the step with u~ frozen; the fluid gets the step-averaged drag, the
+        // momentum exchanged divided by dt
+        const double e1 = -expm1(-dt / t);      // 1 - exp(-dt/tau)
+        for (int d = 0; d < 3; ++d) {
+            double ut = up[d] - vs[d];
+            double vd = B.v[d * np + p];
+            double w = ut + t * B.gb[d];         // velocity the particle relaxes to
+            vn[d] = vd - (vd - w) * e1;
+            xn[d] = xp[d] + dt * w + t * (vd - w) * e1;
+            D[d] = B.m_p * (vn[d] - vd) / dt - B.m_p * B.gb[d];
+        }
     }
     for (int d = 0; d < 3; ++d) {
         hx[d * np + p] = xp[d];
         if (hdD) hdD[d * np + p] = D[d];
         if (hdF) hdF[d * np + p] = (float)D[d];
-        vn[d] += dt * D[d] / B.m_p;
-        vn[d] += dt * B.gb[d];
     }
     for (int d = 0; d < 3; ++d) {
         double L = B.L[d];

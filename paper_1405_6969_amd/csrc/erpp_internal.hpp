@@ -33,7 +33,7 @@ struct DevBox {
     int64_t cell_off;    // first cell of this box in the concatenated cell space (erpp_bin)
     int64_t key_off;     // first key of this box in the step's (row, x-block) key space
     int32_t nxb;         // x-blocks per cell row
-    int32_t pad0;
+    int32_t integ;       // particle integrator: 0 explicit Euler, 1 exponential
     int64_t blk_p;       // first block of this box in particle launches
     int64_t blk_t;       // first block of this box in tile launches
     int64_t blk_b;       // first block of this box in (cell row, x-block) launches

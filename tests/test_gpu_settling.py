@@ -129,3 +129,71 @@ def test_settling_unresolved_sigma():
     errs = [_terminal_error(48, s * dx, 0.0625) for s in (1.0, 0.5, 0.3)]
     print("sigma_R/Dx 1, 0.5, 0.3:", [f"{e:.4f}" for e in errs])
     assert all(0.0 < e < 0.03 for e in errs)
+
+
+@pytest.mark.parametrize("prec", [erpp.F32_FAST, erpp.F64_PLAIN])
+def test_exponential_integrator_matches_oracle(prec):
+    """ERPP_EXPONENTIAL through the coupling step (frozen k^-5/3 carrier, gravity,
+    Stokes times 0.01 and 0.05 with dt = 0.03, where explicit Euler diverges for
+    the first population), 12 steps, against the oracle with the same
+    integrator.  Bars of the coupling step: f 1e-5 / 1e-12, v 1e-6 / 1e-13;
+    x within steps * dt * (v bar) * max|v| (FP32) and 1e-12 (FP64)."""
+    _cuda()
+    import workloads
+    from helpers import carrier_for, periodic_diff, tolerances, upload
+    spec = workloads.BoxSpec(n=(32, 28, 24), L=(2 * math.pi, 2 * math.pi * 28 / 32,
+                                                 2 * math.pi * 24 / 32), np_=1500,
+                             carrier="k53", kmax=6.0, tau=(0.01, 0.05), nu=0.05,
+                             mass_loading=0.5, placement="clustered", n_blobs=5,
+                             blob_radius_dx=3.0, seed=workloads.SEED_BASE + 77)
+    box = workloads.make_box(spec)
+    M, dt, steps = 3, 0.03, 12
+    gb = (0.3, -1.0, 0.2)
+    db = upload(box, M, prec)
+    P = oracle.params_for_box(box, M, dt, 1)
+    P.g = (type(P.g))(*gb)
+    P.integrator = 1
+    run = oracle.Run(P, carrier_for(box, prec), box.x, box.v, box.tau)
+    tf, tv = tolerances(prec)
+    with erpp.Plan([db], M, dt, precision=prec) as plan:
+        plan.set_body_force(0, gb)
+        plan.set_integrator(erpp.EXPONENTIAL)
+        for n in range(steps):
+            plan.step(n)
+            fo, _ = run.step(want_f=True)
+            if n >= M:
+                assert rel_l2(db.f.double().cpu().numpy(), fo) <= tf, n
+        torch.cuda.synchronize()
+    assert rel_l2(db.v.cpu().numpy(), run.v) <= tv
+    # positions take dt (u~ + tau g_b) directly: the displacement the velocity bar allows
+    ex = np.max(np.abs(periodic_diff(db.x.cpu().numpy(), run.x, box.L)))
+    assert ex <= (1e-12 if prec == erpp.F64_PLAIN else steps * dt * tv * np.max(np.abs(run.v)))
+
+
+def test_exponential_integrator_settles_with_large_steps():
+    """The coupled settling particle with tau_p = dt / 3 (explicit Euler would
+    diverge): the exponential integrator relaxes to the continuous uncoupled
+    solution v_t (1 - e^{-t/tau_p}) within the d_p / sigma_R error of the
+    scheme (d_p / sigma_R = 0.125)."""
+    _cuda()
+    N, sigma, ratio = 24, L / 24, 0.125
+    eps = sigma ** 2 / (2 * NU)
+    dt = eps / M
+    tau = dt / 3
+    m_p = 3 * math.pi * RHO * NU * ratio * sigma * tau
+    dx = L / N
+    x = np.array([[L / 2 + 0.3 * dx], [L / 2], [L / 2]])
+    db = erpp.device_box((N,) * 3, (L,) * 3, x, np.zeros((3, 1)), np.array([tau], np.float32),
+                         np.zeros((3, N, N, N)), M, m_p, RHO, NU, sigma)
+    K = 60
+    with erpp.Plan([db], M, dt) as plan, erpp.Fluid((N,) * 3, (L,) * 3, NU, dt) as fl:
+        plan.set_body_force(0, (G, 0.0, 0.0))
+        plan.set_integrator(erpp.EXPONENTIAL)
+        plan.run_coupled([fl], 0, K, graph=True)
+        torch.cuda.synchronize()
+    tau32 = float(np.float32(tau))
+    v_t = tau32 * G
+    v = db.v[0, 0].item() - db.u[0].double().mean().item()
+    err = v / (v_t * (1 - math.exp(-K * dt / tau32))) - 1
+    print(f"exponential integrator, dt/tau = 3: terminal error {err:.4f}")
+    assert np.isfinite(err) and 0.0 < err < 0.06
