@@ -41,6 +41,11 @@ def _round(a, prec):
     ((33, 20, 17), (2.0, 1.3, 1.1)),           # odd and ragged
     ((64, 48, 40), (6.283185307179586, 4.71238898038469, 3.9269908169872414)),
     ((2, 16, 9), (1.0, 2.0, 1.5)),             # degenerate: x holds only the mean and Nyquist
+    # powers of two: the library's own transforms
+    ((32, 16, 8), (2.0, 1.0, 0.5)),
+    ((64, 32, 128), (3.0, 1.5, 6.0)),
+    ((4, 2, 2), (1.0, 0.5, 0.5)),              # smallest sizes of the own transforms
+    ((256, 128, 128), (12.566370614359172, 6.283185307179586, 6.283185307179586)),
 ])
 def test_fluid_step_matches_oracle(prec, n, L):
     _cuda()
