@@ -36,7 +36,7 @@ class Params(C.Structure):
                 ("m_p", C.c_double), ("rho_f", C.c_double), ("nu", C.c_double),
                 ("sigma", C.c_double), ("cutoff", C.c_double), ("shear", C.c_double),
                 ("M", C.c_int32), ("dt", C.c_double), ("self_correction", C.c_int32),
-                ("g", C.c_double * 3), ("integrator", C.c_int32)]
+                ("g", C.c_double * 3), ("integrator", C.c_int32), ("a_p", C.c_double)]
 
 
 _lib = None
@@ -58,8 +58,11 @@ def _load():
         lib.oracle_self_disturbance.argtypes = [P, d, d, d, d]
         lib.oracle_gather.argtypes = [P, d, d, d]
         lib.oracle_step.argtypes = [P, C.c_int64, d, d, d, f32, d, d, i32, i32, d, d]
+        lib.oracle_self_laplacian.argtypes = [P, d, d, d, d]
+        lib.oracle_grid_laplacian.argtypes = [P, d, d, d]
         for fn in (lib.oracle_bin, lib.oracle_deposit, lib.oracle_normalisation,
-                   lib.oracle_self_disturbance, lib.oracle_gather, lib.oracle_step):
+                   lib.oracle_self_disturbance, lib.oracle_gather, lib.oracle_step,
+                   lib.oracle_self_laplacian, lib.oracle_grid_laplacian):
             fn.restype = None
         _lib = lib
     return _lib
@@ -74,7 +77,8 @@ def _f64(a):
 
 
 def make_params(n, L, np_, m_p, rho_f, nu, sigma, cutoff=3.0, shear=0.0, M=1,
-                dt=1e-3, self_correction=1, g=(0.0, 0.0, 0.0), integrator=0) -> Params:
+                dt=1e-3, self_correction=1, g=(0.0, 0.0, 0.0), integrator=0,
+                a_p=0.0) -> Params:
     P = Params()
     P.n = (C.c_int32 * 3)(*[int(v) for v in n])
     P.L = (C.c_double * 3)(*[float(v) for v in L])
@@ -84,6 +88,7 @@ def make_params(n, L, np_, m_p, rho_f, nu, sigma, cutoff=3.0, shear=0.0, M=1,
     P.M, P.dt, P.self_correction = int(M), float(dt), int(self_correction)
     P.g = (C.c_double * 3)(*[float(a) for a in g])
     P.integrator = int(integrator)
+    P.a_p = float(a_p)
     for d in range(3):
         dxd = P.L[d] / P.n[d]
         R = int(np.ceil(P.cutoff * P.sigma / dxd))
@@ -159,6 +164,26 @@ def self_disturbance(P: Params, x, Xp, Dp):
     _load().oracle_self_disturbance(C.byref(Q), _ptr(x, C.c_double), _ptr(Xp, C.c_double),
                                     _ptr(Dp, C.c_double), _ptr(vs, C.c_double))
     return vs
+
+
+def self_laplacian(P: Params, x, Xp, Dp):
+    """Laplacian of the closed-form self-disturbance (Faxen term, self part)."""
+    x, Xp, Dp = _f64(x), _f64(Xp), _f64(Dp)
+    Q = _with_np(P, x.shape[1])
+    ls = np.empty_like(x)
+    _load().oracle_self_laplacian(C.byref(Q), _ptr(x, C.c_double), _ptr(Xp, C.c_double),
+                                  _ptr(Dp, C.c_double), _ptr(ls, C.c_double))
+    return ls
+
+
+def grid_laplacian(P: Params, u, x):
+    """Trilinear interpolation of the 7-point nodal Laplacian of u at x."""
+    u, x = _f64(u), _f64(x)
+    Q = _with_np(P, x.shape[1])
+    lu = np.empty_like(x)
+    _load().oracle_grid_laplacian(C.byref(Q), _ptr(u, C.c_double), _ptr(x, C.c_double),
+                                  _ptr(lu, C.c_double))
+    return lu
 
 
 def gather(P: Params, u, x):

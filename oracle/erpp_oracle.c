@@ -285,6 +285,86 @@ void oracle_self_disturbance(const oracle_params *P, const double *x,
 
 /* --------------------------------------------------------------- gather --- */
 
+/* Laplacian of the App. E disturbance.  That disturbance is the projection
+ * of the regularised impulse -(dt/rho_f) D g(r; s), s = sigma_s^2 (forcing,
+ * heat semigroup, projection), and the Laplacian commutes with the
+ * projection, so lap v = -(dt/rho_f) [D lap g - grad (D . grad g)]; with the
+ * Gaussian's derivatives  lap g = g (r^2/s^2 - 3/s) and
+ * d_i d_j g = g (r_i r_j / s^2 - delta_ij / s):
+ *   lap v_c = -(dt/rho_f) g [D_c (r^2/s^2 - 2/s) - r_c (D.r)/s^2]. */
+static void self_laplacian_one(const oracle_params *P, const double r[3],
+                               const double Dp[3], double ls[3])
+{
+    const double s = P->sigma * P->sigma + 2.0 * P->nu * P->dt;
+    const double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const double g = pow(2.0 * ORACLE_PI * s, -1.5) * exp(-rr / (2.0 * s));
+    const double Dr = Dp[0] * r[0] + Dp[1] * r[1] + Dp[2] * r[2];
+    int c;
+    for (c = 0; c < 3; ++c)
+        ls[c] = -(P->dt / P->rho_f) * g * (Dp[c] * (rr / (s * s) - 2.0 / s) - r[c] * Dr / (s * s));
+}
+
+void oracle_self_laplacian(const oracle_params *P, const double *x,
+                           const double *Xp, const double *Dp, double *ls)
+{
+    const int64_t np = P->np;
+    int64_t p;
+    for (p = 0; p < np; ++p) {
+        double r[3], D[3], out[3];
+        int d;
+        for (d = 0; d < 3; ++d) {
+            double rd = x[d * np + p] - Xp[d * np + p];
+            rd -= P->L[d] * nearbyint(rd / P->L[d]);
+            r[d] = rd;
+            D[d] = Dp[d * np + p];
+        }
+        self_laplacian_one(P, r, D, out);
+        for (d = 0; d < 3; ++d) ls[d * np + p] = out[d];
+    }
+}
+
+/* 7-point Laplacian of component c at node (i, j, k), periodic. */
+static double node_laplacian(const oracle_params *P, const double *u, int c, int64_t i,
+                             int64_t j, int64_t k)
+{
+    const int64_t Nx = P->n[0], Ny = P->n[1], Nz = P->n[2];
+    const double *uc = u + (int64_t)c * Nx * Ny * Nz;
+    const double h0 = P->L[0] / Nx, h1 = P->L[1] / Ny, h2 = P->L[2] / Nz;
+#define U_AT(a, b, d) uc[(imod(d, Nz) * Ny + imod(b, Ny)) * Nx + imod(a, Nx)]
+    const double u0 = U_AT(i, j, k);
+    const double lx = (U_AT(i + 1, j, k) - 2.0 * u0 + U_AT(i - 1, j, k)) / (h0 * h0);
+    const double ly = (U_AT(i, j + 1, k) - 2.0 * u0 + U_AT(i, j - 1, k)) / (h1 * h1);
+    const double lz = (U_AT(i, j, k + 1) - 2.0 * u0 + U_AT(i, j, k - 1)) / (h2 * h2);
+#undef U_AT
+    return lx + ly + lz;
+}
+
+void oracle_grid_laplacian(const oracle_params *P, const double *u, const double *x,
+                           double *lu)
+{
+    const int64_t np = P->np;
+    int64_t p;
+    for (p = 0; p < np; ++p) {
+        int32_t b[3];
+        double phi[3], w[3][2], acc[3] = {0.0, 0.0, 0.0};
+        int d, a, bb, cc, c;
+        for (d = 0; d < 3; ++d) {
+            cell_of(x[d * np + p], P->L[d], P->n[d], &b[d], &phi[d]);
+            w[d][0] = 1.0 - phi[d];
+            w[d][1] = phi[d];
+        }
+        for (cc = 0; cc < 2; ++cc)
+            for (bb = 0; bb < 2; ++bb)
+                for (a = 0; a < 2; ++a) {
+                    double wt = w[0][a] * w[1][bb] * w[2][cc];
+                    for (c = 0; c < 3; ++c)
+                        acc[c] += wt * node_laplacian(P, u, c, (int64_t)b[0] + a,
+                                                      (int64_t)b[1] + bb, (int64_t)b[2] + cc);
+                }
+        for (c = 0; c < 3; ++c) lu[c * np + p] = acc[c];
+    }
+}
+
 void oracle_gather(const oracle_params *P, const double *u, const double *x,
                    double *up)
 {
@@ -331,6 +411,9 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
     const int64_t lvl = (int64_t)3 * np; /* doubles per ring level */
     double *vs = (double *)calloc((size_t)(3 * np > 0 ? 3 * np : 1), sizeof(double));
     double *up = (double *)malloc(sizeof(double) * (size_t)(3 * np > 0 ? 3 * np : 1));
+    double *ls = (double *)calloc((size_t)(3 * np > 0 ? 3 * np : 1), sizeof(double));
+    double *lu = (double *)calloc((size_t)(3 * np > 0 ? 3 * np : 1), sizeof(double));
+    const double fax = P->a_p * P->a_p / 6.0;
     int64_t p;
 
     /* 1. forcing from the drag delayed by eps_R = M dt */
@@ -347,7 +430,12 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
     if (P->self_correction && n >= M + 1) {
         int64_t slot = (n - 1 - M) % (M + 1);
         oracle_self_disturbance(P, x, ring_x + slot * lvl, ring_d + slot * lvl, vs);
+        if (fax != 0.0)
+            oracle_self_laplacian(P, x, ring_x + slot * lvl, ring_d + slot * lvl, ls);
     }
+    /* Faxen correction of the drag (eq. force_particle, first line):
+       (a_p^2/6) lap u~ with u~ = u - v_self */
+    if (fax != 0.0) oracle_grid_laplacian(P, u, x, lu);
     /* 3. carrier velocity at the particles */
     oracle_gather(P, u, x, up);
     /* 4. drag, history, explicit Euler */
@@ -363,6 +451,7 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
             if (P->integrator == 0) {
                 for (d = 0; d < 3; ++d) {
                     double ut = up[d * np + p] - vs[d * np + p];
+                    ut += fax * (lu[d * np + p] - ls[d * np + p]);
                     D[d] = P->m_p * (ut - v[d * np + p]) / t;
                 }
                 for (d = 0; d < 3; ++d) {
@@ -387,6 +476,7 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
                 for (d = 0; d < 3; ++d) {
                     double ut = up[d * np + p] - vs[d * np + p];
                     double v0 = v[d * np + p];
+                    ut += fax * (lu[d * np + p] - ls[d * np + p]);
                     double w = ut + t * P->g[d];
                     double v1 = w + (v0 - w) * E;
                     hx[d * np + p] = x[d * np + p];
@@ -411,4 +501,6 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
     }
     free(vs);
     free(up);
+    free(ls);
+    free(lu);
 }

@@ -38,6 +38,7 @@ typedef struct {
     int32_t self_correction; /* 1: remove the closed-form self disturbance */
     double  g[3];        /* body acceleration of the particles, (m_p - m_f) g / m_p */
     int32_t integrator;  /* 0 explicit Euler, 1 exact linear drag over the step */
+    double  a_p;         /* particle radius of the Faxen term (a_p^2/6) lap u~; 0 = off */
 } oracle_params;
 
 /* Cell key of each position and a stable counting sort by key.
@@ -58,6 +59,15 @@ void oracle_normalisation(const oracle_params *P, const double *X, double *Z);
  * earlier at (Xp, Dp): App. E, with width sigma_s^2 = sigma^2 + 2 nu dt. */
 void oracle_self_disturbance(const oracle_params *P, const double *x,
                              const double *Xp, const double *Dp, double *vs);
+
+/* Laplacian of the closed-form self-disturbance at x (same arguments as
+ * oracle_self_disturbance): the Faxen term's self part. */
+void oracle_self_laplacian(const oracle_params *P, const double *x,
+                           const double *Xp, const double *Dp, double *ls);
+
+/* Trilinear interpolation at x of the 7-point nodal Laplacian of u. */
+void oracle_grid_laplacian(const oracle_params *P, const double *u, const double *x,
+                           double *lu);
 
 /* Trilinear interpolation of the carrier u at x plus the mean shear. */
 void oracle_gather(const oracle_params *P, const double *u, const double *x,

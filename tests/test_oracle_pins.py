@@ -512,3 +512,79 @@ def test_k53_field_is_divergence_free_and_scaled():
     KZ, KY, KX = np.meshgrid(k, k, k, indexing="ij")
     div = KX * uh[0] + KY * uh[1] + KZ * uh[2]
     assert np.max(np.abs(div)) < 1e-9 * np.max(np.abs(uh[0]))
+
+
+# ------------------------------------------------------------- Faxen term --
+
+def test_p13_self_laplacian_is_the_laplacian_of_the_app_e_closed_form():
+    """The Faxen term needs lap v_self.  Its closed form (the Gaussian's second
+    derivatives through the projection) against a fourth-order finite-difference
+    Laplacian of the App. B tensor form of the App. E disturbance."""
+    box = workloads.tiny_box(81, n=(32, 32, 32), np_=1, sigma_dx=1.5)
+    dt = 2e-3
+    P = _params(box, M=2, dt=dt)
+    s = math.sqrt(P.sigma ** 2 + 2 * P.nu * dt)
+    rng = np.random.default_rng(5)
+    D = np.array([0.7, -0.4, 1.1])
+    h = 2e-3 * s
+    for _ in range(12):
+        r = rng.normal(size=3)
+        r *= rng.uniform(0.2, 3.0) * s / np.linalg.norm(r)
+        x = (np.array([0.5, 0.5, 0.5]) * np.array(box.L) + r)[:, None]
+        Xp = (np.array([0.5, 0.5, 0.5]) * np.array(box.L))[:, None]
+        got = oracle.self_laplacian(P, x, Xp, D[:, None])[:, 0]
+
+        def v(rr):
+            return brute.green_tensor_velocity(rr[:, None], D[:, None], s, dt, P.rho_f)[:, 0]
+        lap = np.zeros(3)
+        for d in range(3):
+            e = np.zeros(3)
+            e[d] = h
+            lap += (-v(r + 2 * e) + 16 * v(r + e) - 30 * v(r) + 16 * v(r - e) - v(r - 2 * e)) \
+                / (12 * h * h)
+        assert np.allclose(got, lap, rtol=1e-5, atol=1e-6 * np.max(np.abs(lap)))
+
+
+def test_p14_grid_laplacian_of_a_fourier_mode():
+    """On the grid, the 7-point Laplacian of a Fourier mode is the mode times
+    -sum_d (4/h_d^2) sin^2(k_d h_d/2); the interpolated value is that times the
+    trilinear interpolation of the mode, and the symbol tends to -|k|^2 at
+    second order in h."""
+    errs = []
+    for N in (16, 32):
+        n, L = (N, N + 4, N - 2), (2.0, 2.5, 1.8)
+        box = workloads.tiny_box(82, n=n, L=L, np_=50, carrier="zero")
+        P = _params(box, M=2, dt=1e-3)
+        m = (2, -1, 1)
+        k = np.array([2 * math.pi * m[d] / L[d] for d in range(3)])
+        h = np.array([L[d] / n[d] for d in range(3)])
+        ax = [np.arange(n[d]) * h[d] for d in range(3)]
+        z, y, x = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+        ph = np.cos(k[0] * x + k[1] * y + k[2] * z + 0.4)
+        u = np.stack([ph, 2 * ph, -ph])
+        sym = -np.sum(4 / h ** 2 * np.sin(k * h / 2) ** 2)
+        got = oracle.grid_laplacian(P, u, box.x)
+        want = sym * oracle.gather(P, u, box.x)
+        assert np.allclose(got, want, rtol=1e-12, atol=1e-12 * np.max(np.abs(want)))
+        errs.append(abs(sym / -(k @ k) - 1))
+    assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_p15_faxen_term_enters_the_drag():
+    """eq. force_particle, first line: D = m_p (u~ + (a_p^2/6) lap u~ - v)/tau.
+    Before any self term exists (n <= M) a step with radius a_p differs from
+    one without by m_p (a_p^2/6) lap u / tau in the drag."""
+    box = workloads.tiny_box(83, n=(24, 24, 24), np_=30)
+    dt, a = 1e-3, 0.05
+    Ds = []
+    for ap in (0.0, a):
+        P = _params(box, M=3, dt=dt)
+        P.a_p = ap
+        run = oracle.Run(P, box.u, box.x, box.v, box.tau)
+        _, D = run.step(want_f=False)
+        Ds.append(D)
+    P = _params(box, M=3, dt=dt)
+    lap = oracle.grid_laplacian(P, box.u, box.x)
+    tau = box.tau.astype(np.float64)[None, :]
+    want = box.m_p * (a * a / 6.0) * lap / tau
+    assert np.allclose(Ds[1] - Ds[0], want, rtol=1e-10, atol=1e-12 * np.max(np.abs(want)))
