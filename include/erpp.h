@@ -141,6 +141,15 @@ erpp_status erpp_plan_get_tile(const erpp_plan *plan, int32_t tile[3]);
  * ERPP_EINVAL for a bad plan or index or a non-finite component. */
 erpp_status erpp_plan_set_body_force(erpp_plan *plan, int32_t ibox, const double g[3]);
 
+/* Faxen correction of the drag of box `ibox` (eq. force_particle, first line):
+ * D = m_p (u~ + (a_p^2/6) lap u~ - v)/tau_p with a_p the particle radius
+ * (0, the default, turns it off).  lap u~ = the trilinear interpolation of the
+ * 7-point nodal Laplacian of the carrier minus the Laplacian of the closed-form
+ * self-disturbance (the projected Gaussian's second derivatives).  Added mass
+ * and the Basset history force are not provided.  Synchronises the device.
+ * ERPP_EINVAL for a bad plan, index or radius. */
+erpp_status erpp_plan_set_faxen(erpp_plan *plan, int32_t ibox, double a_p);
+
 /* Particle integrator of every box (default ERPP_EULER).  The self-disturbance
  * removed from u~ is the same App. E closed form for both (the fluid receives
  * one forcing step of the handed-over drag either way).  Applies to later

@@ -23,7 +23,7 @@ EXPORTS = ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile", "erpp
            "erpp_plan_bins", "erpp_bin", "erpp_scatter", "erpp_gather", "erpp_step", "erpp_run",
            "erpp_stage_times", "erpp_plan_destroy", "erpp_status_string", "erpp_last_error",
            "erpp_fluid_create", "erpp_fluid_step", "erpp_fluid_destroy", "erpp_run_coupled",
-           "erpp_plan_set_body_force", "erpp_plan_set_integrator"]
+           "erpp_plan_set_body_force", "erpp_plan_set_integrator", "erpp_plan_set_faxen"]
 
 
 class ErppError(RuntimeError):
@@ -80,11 +80,12 @@ def load(path: str = LIB_PATH):
     lib.erpp_run_coupled.argtypes = [vp, C.POINTER(vp), i64, i64, i32, vp]
     lib.erpp_plan_set_body_force.argtypes = [vp, i32, C.POINTER(d)]
     lib.erpp_plan_set_integrator.argtypes = [vp, C.c_int]
+    lib.erpp_plan_set_faxen.argtypes = [vp, i32, d]
     for name in ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile",
                  "erpp_plan_tune", "erpp_plan_bins", "erpp_bin", "erpp_scatter", "erpp_gather",
                  "erpp_step", "erpp_run", "erpp_stage_times", "erpp_fluid_create",
                  "erpp_fluid_step", "erpp_run_coupled", "erpp_plan_set_body_force",
-                 "erpp_plan_set_integrator"]:
+                 "erpp_plan_set_integrator", "erpp_plan_set_faxen"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -205,6 +206,10 @@ class Plan:
         _check(self.lib.erpp_plan_set_body_force(self.h, int(ibox),
                                                  (C.c_double * 3)(*[float(a) for a in g])),
                "erpp_plan_set_body_force")
+
+    def set_faxen(self, ibox: int, a_p: float):
+        """Particle radius of the Faxen term (a_p^2/6) lap u~ in the drag of box ibox."""
+        _check(self.lib.erpp_plan_set_faxen(self.h, int(ibox), float(a_p)), "erpp_plan_set_faxen")
 
     def set_integrator(self, kind: int):
         """EULER (explicit Euler) or EXPONENTIAL (exact linear drag over the step)."""

@@ -229,6 +229,63 @@ __device__ __forceinline__ void trilinear(const DevBox &B, const T *__restrict__
     out[2] = acc2;
 }
 
+// index i in [-1, N] taken periodically into [0, N)
+__device__ __forceinline__ int wrap_node(int i, int N) { return i < 0 ? i + N : (i >= N ? i - N : i); }
+
+// Trilinear interpolation at xp of the 7-point nodal Laplacian of u (the grid
+// part of the Faxen term); the mean shear is linear and adds nothing.  FP64.
+template <typename T>
+__device__ void trilinear_laplacian(const DevBox &B, const T *__restrict__ u, const double xp[3],
+                                    double out[3]) {
+    int b[3];
+    double ph[3];
+    for (int d = 0; d < 3; ++d) cell_of(xp[d], B.L[d], B.dx[d], B.n[d], b[d], ph[d]);
+    const int Nx = B.n[0], Ny = B.n[1], Nz = B.n[2];
+    const int64_t ng = (int64_t)Nx * Ny * Nz;
+    const double h0 = 1.0 / (B.dx[0] * B.dx[0]), h1 = 1.0 / (B.dx[1] * B.dx[1]),
+                 h2 = 1.0 / (B.dx[2] * B.dx[2]);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int c2 = 0; c2 < 2; ++c2)
+        for (int c1 = 0; c1 < 2; ++c1)
+            for (int c0 = 0; c0 < 2; ++c0) {
+                const double w = (c0 ? ph[0] : 1.0 - ph[0]) * (c1 ? ph[1] : 1.0 - ph[1]) *
+                                 (c2 ? ph[2] : 1.0 - ph[2]);
+                const int i = wrap_node(b[0] + c0, Nx), j = wrap_node(b[1] + c1, Ny),
+                          k = wrap_node(b[2] + c2, Nz);
+                const int im = wrap_node(i - 1, Nx), ip = wrap_node(i + 1, Nx);
+                const int jm = wrap_node(j - 1, Ny), jp = wrap_node(j + 1, Ny);
+                const int km = wrap_node(k - 1, Nz), kp = wrap_node(k + 1, Nz);
+                const int64_t row = ((int64_t)k * Ny + j) * Nx;
+                for (int c = 0; c < 3; ++c) {
+                    const T *uc = u + c * ng;
+                    const double u0 = (double)uc[row + i];
+                    const double lx = ((double)uc[row + ip] - 2.0 * u0 + (double)uc[row + im]) * h0;
+                    const double ly = ((double)uc[((int64_t)k * Ny + jp) * Nx + i] - 2.0 * u0 +
+                                       (double)uc[((int64_t)k * Ny + jm) * Nx + i]) * h1;
+                    const double lz = ((double)uc[((int64_t)kp * Ny + j) * Nx + i] - 2.0 * u0 +
+                                       (double)uc[((int64_t)km * Ny + j) * Nx + i]) * h2;
+                    acc[c] += w * (lx + ly + lz);
+                }
+            }
+    out[0] = acc[0];
+    out[1] = acc[1];
+    out[2] = acc[2];
+}
+
+// Laplacian of the closed-form self-disturbance (the self part of the Faxen
+// term): the disturbance is the projection of -(dt/rho_f) D g(r; s), and the
+// Laplacian commutes with the projection, so with g's second derivatives
+// lap v_c = pref e^{-r^2/(2s)} [D_c (r^2/s^2 - 2/s) - r_c (D.r)/s^2],
+// pref = -(dt/rho_f)(2 pi s)^{-3/2}, s = sigma_s^2.  FP64.
+__device__ __forceinline__ void self_laplacian64(const double r[3], const double D[3], double s,
+                                                 double pref, double out[3]) {
+    const double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const double e = pref * exp(-rr / (2.0 * s));
+    const double Dr = D[0] * r[0] + D[1] * r[1] + D[2] * r[2];
+    const double is = 1.0 / s;
+    for (int c = 0; c < 3; ++c) out[c] = e * (D[c] * (rr * is * is - 2.0 * is) - r[c] * Dr * is * is);
+}
+
 // Drag, history write, explicit Euler and periodic wrap (Lees-Edwards velocity
 // jump in y when a mean shear is present).  FP64.
 __device__ __forceinline__ void update_particle(const DevBox &B, int64_t p, double dt,

@@ -46,6 +46,7 @@ struct DevBox {
     double two_s2;       // 2 sigma^2
     double m_p, rho_f, shear;
     double gb[3];        // body acceleration of the particles, (m_p - m_f) g / m_p
+    double fax;          // Faxen coefficient a_p^2 / 6 (0: no Faxen term)
     double s2s;          // sigma_s^2 = sigma^2 + 2 nu dt  (self-disturbance width)
     double pref;         // -(dt/rho_f) (2 pi sigma_s^2)^(-3/2)
     float dxf[3];

@@ -762,6 +762,28 @@ __global__ void __launch_bounds__(kBlock) k_update(const DevBox *__restrict__ Bs
         vs[1] = v1;
         vs[2] = v2;
     }
+    if (B.fax != 0.0) {
+        // Faxen term (a_p^2/6) lap u~: grid Laplacian minus the self part
+        double lu[3], ls[3] = {0.0, 0.0, 0.0};
+        trilinear_laplacian<float>(B, (const float *)B.u, xp, lu);
+        if (selfc && n >= M + 1) {
+            const int64_t ss = (n - 1 - M) % (M + 1);
+            const double *Xs = B.ring_x + ss * 3 * np;
+            const float *Ds = (const float *)B.ring_d + ss * 3 * np;
+            double r[3], D[3];
+            for (int d = 0; d < 3; ++d) {
+                double rd = xp[d] - Xs[d * np + p];
+                rd -= B.L[d] * rint(rd / B.L[d]);
+                r[d] = rd;
+                D[d] = (double)Ds[d * np + p];
+            }
+            self_laplacian64(r, D, B.s2s, B.pref, ls);
+        }
+        for (int d = 0; d < 3; ++d) {
+            up[d] += B.fax * lu[d];
+            vs[d] += B.fax * ls[d];
+        }
+    }
     const int64_t sw = n % (M + 1);
     update_particle(B, p, dt, xp, up, vs, B.ring_x + sw * 3 * np, nullptr,
                     (float *)B.ring_d + sw * 3 * np);

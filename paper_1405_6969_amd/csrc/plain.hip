@@ -136,6 +136,17 @@ __global__ void __launch_bounds__(kBlock) k_plain_update(const DevBox *__restric
             D[d] = Ds[d * np + p];
         }
         self_disturbance64(r, D, B.s2s, B.pref, vs);
+        if (B.fax != 0.0) {
+            double ls[3];
+            self_laplacian64(r, D, B.s2s, B.pref, ls);
+            for (int d = 0; d < 3; ++d) vs[d] += B.fax * ls[d];
+        }
+    }
+    if (B.fax != 0.0) {
+        // Faxen term (a_p^2/6) lap u~, grid part (the self part is above)
+        double lu[3];
+        trilinear_laplacian<double>(B, (const double *)B.u, xp, lu);
+        for (int d = 0; d < 3; ++d) up[d] += B.fax * lu[d];
     }
     const int64_t sw = n % (M + 1);
     update_particle(B, p, dt, xp, up, vs, B.ring_x + sw * 3 * np,

@@ -197,3 +197,44 @@ def test_exponential_integrator_settles_with_large_steps():
     err = v / (v_t * (1 - math.exp(-K * dt / tau32))) - 1
     print(f"exponential integrator, dt/tau = 3: terminal error {err:.4f}")
     assert np.isfinite(err) and 0.0 < err < 0.06
+
+
+@pytest.mark.parametrize("prec", [erpp.F32_FAST, erpp.F64_PLAIN])
+def test_faxen_term_matches_oracle(prec):
+    """The Faxen correction (eq. force_particle, first line) in the two-way
+    coupled loop: k^-5/3 carrier, particle radius 0.6 dx, 12 coupled steps,
+    against the oracle's coupled loop with the same radius.  Bars: the coupled
+    test's (v 1e-6 / 1e-12, u 1e-5 / 1e-12).  The term must matter: the run
+    without it differs by far more than the bar."""
+    _cuda()
+    import workloads
+    from helpers import carrier_for, upload
+    n = (32, 32, 32)
+    spec = workloads.BoxSpec(n=n, L=(L,) * 3, np_=1500, carrier="k53", kmax=10.0,
+                             tau=(0.02, 0.05), nu=0.05, mass_loading=2.0, placement="clustered",
+                             n_blobs=6, blob_radius_dx=3.0, seed=workloads.SEED_BASE + 91)
+    box = workloads.make_box(spec)
+    Mx, dt, steps = 3, 2e-3, 12
+    a_p = 0.6 * box.dx[0]
+    out = {}
+    for ap in (0.0, a_p):
+        db = upload(box, Mx, prec)
+        with erpp.Plan([db], Mx, dt, precision=prec) as plan, \
+                erpp.Fluid(box.n, box.L, box.spec.nu, dt, precision=prec) as fl:
+            plan.set_faxen(0, ap)
+            plan.run_coupled([fl], 0, steps, graph=True)
+            torch.cuda.synchronize()
+        out[ap] = (db.v.cpu().numpy(), db.u.double().cpu().numpy())
+    P = oracle.params_for_box(box, Mx, dt, 1)
+    P.a_p = a_p
+    run = oracle.Run(P, carrier_for(box, prec), box.x, box.v, box.tau)
+    for _ in range(steps):
+        f, _ = run.step(want_f=True)
+        run.u = ofluid.fluid_step(box.n, box.L, box.spec.nu, dt, run.u, f)
+    v, u = out[a_p]
+    ev, eu = rel_l2(v, run.v), rel_l2(u, run.u)
+    effect = rel_l2(out[0.0][0], run.v)
+    print(f"prec {prec}: Faxen v {ev:.3e}, u {eu:.3e}; without the term v differs by {effect:.3e}")
+    tv, tu = (1e-12, 1e-12) if prec == erpp.F64_PLAIN else (1e-6, 1e-5)
+    assert ev <= tv and eu <= tu
+    assert effect > 100 * tv
