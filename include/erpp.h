@@ -146,8 +146,8 @@ erpp_status erpp_plan_set_body_force(erpp_plan *plan, int32_t ibox, const double
  * (0, the default, turns it off).  lap u~ = the trilinear interpolation of the
  * 7-point nodal Laplacian of the carrier minus the Laplacian of the closed-form
  * self-disturbance (the projected Gaussian's second derivatives).  Added mass
- * and the Basset history force are not provided.  Synchronises the device.
- * ERPP_EINVAL for a bad plan, index or radius. */
+ * and the Basset history force are not provided.  Synchronises the device and
+ * invalidates captured graphs.  ERPP_EINVAL for a bad plan, index or radius. */
 erpp_status erpp_plan_set_faxen(erpp_plan *plan, int32_t ibox, double a_p);
 
 /* Particle integrator of every box (default ERPP_EULER).  The self-disturbance

@@ -439,6 +439,7 @@ erpp_status erpp_plan_set_faxen(erpp_plan *p, int32_t ibox, double a_p) {
     if (ibox < 0 || ibox >= p->nbox) return fail(ERPP_EINVAL, "ibox %d out of range", ibox);
     if (!std::isfinite(a_p) || a_p < 0.0) return fail(ERPP_EINVAL, "a_p must be finite and >= 0");
     p->hbox[ibox].fax = a_p * a_p / 6.0;
+    drop_graph(p);     // the update kernel's instance depends on it
     HIP_OR_RETURN(hipDeviceSynchronize());
     HIP_OR_RETURN(hipMemcpy(p->dbox + ibox, &p->hbox[ibox], sizeof(erpp::DevBox),
                             hipMemcpyHostToDevice));

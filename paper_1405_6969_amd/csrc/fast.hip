@@ -722,6 +722,9 @@ __global__ void __launch_bounds__(kBlock) k_gather_sorted(const DevBox *__restri
     up[B.poff + r] = make_double4(u[0], u[1], u[2], 0.0);
 }
 
+// FAX: some box of the plan has a Faxen term (its extra work doubles the
+// registers, so plans without one run the lean instance)
+template <bool FAX>
 __global__ void __launch_bounds__(kBlock) k_update(const DevBox *__restrict__ Bs, int nbox,
                                                    const int64_t *__restrict__ stepp, int M,
                                                    double dt, int selfc,
@@ -762,7 +765,7 @@ __global__ void __launch_bounds__(kBlock) k_update(const DevBox *__restrict__ Bs
         vs[1] = v1;
         vs[2] = v2;
     }
-    if (B.fax != 0.0) {
+    if (FAX && B.fax != 0.0) {
         // Faxen term (a_p^2/6) lap u~: grid Laplacian minus the self part
         double lu[3], ls[3] = {0.0, 0.0, 0.0};
         trilinear_laplacian<float>(B, (const float *)B.u, xp, lu);
@@ -912,7 +915,10 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                 hipLaunchKernelGGL(k_gather_sorted, dim3((unsigned)grid), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->pblocks, P->s.step + 1, P->M, P->s.xs,
                                    P->s.up);
-                hipLaunchKernelGGL(k_update, dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
+                bool fax = false;
+                for (const auto &B : P->hbox) fax = fax || B.fax != 0.0;
+                hipLaunchKernelGGL(fax ? k_update<true> : k_update<false>,
+                                   dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step + 1, P->M, P->dt, P->self_correction,
                                    P->s.up, P->s.sl);
             }

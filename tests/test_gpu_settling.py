@@ -221,6 +221,9 @@ def test_faxen_term_matches_oracle(prec):
         db = upload(box, Mx, prec)
         with erpp.Plan([db], Mx, dt, precision=prec) as plan, \
                 erpp.Fluid(box.n, box.L, box.spec.nu, dt, precision=prec) as fl:
+            if ap > 0:
+                # a graph captured before the radius is set must not be reused
+                plan.run_coupled([fl], 0, 0, graph=True)
             plan.set_faxen(0, ap)
             plan.run_coupled([fl], 0, steps, graph=True)
             torch.cuda.synchronize()
