@@ -198,8 +198,7 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
                                                  double4 *__restrict__ xs,
                                                  int32_t *__restrict__ sl) {
     __shared__ float sP[kMaxOff + 1][kBlock];   // prefix sums of the x factors
-    __shared__ int s_cls[256];                   // reachable row classes, (dz, dy) order
-    __shared__ int s_wcnt[kBlock / 64];
+    __shared__ int s_rng[kMaxOff];               // per mz: reachable my in [lo, hi]
     const int64_t n = *stepp;
     if (n < M) return;
     const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_p; });
@@ -208,37 +207,25 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
     const int64_t p = (int64_t)(blockIdx.x - B.blk_p) * kBlock + tid;
     const float cut = B.R2f + B.guard;
     // row classes (my, mz) whose row can meet the sphere for some offset in the
-    // cell: a deterministic compaction (ballot ranks + wave counts), so the sum
-    // order of Z is fixed
+    // cell: for each mz the reachable my form one interval (the test is convex
+    // in |my|); rows are summed in (mz, my) order, so the order of Z is fixed
     const int mlo1 = B.mlo[1], ny = B.mhi[1] - B.mlo[1] + 1;
     const int mlo2 = B.mlo[2], nz = B.mhi[2] - B.mlo[2] + 1;
-    int ncls = 0;
-    for (int c0 = 0; c0 < ny * nz; c0 += kBlock) {
-        const int k = c0 + tid;
-        bool reach = false;
-        if (k < ny * nz) {
-            const int dy = mlo1 + k % ny, dz = mlo2 + k / ny;
+    if (tid < nz) {
+        const int dz = mlo2 + tid;
+        const float az = (float)(dz >= 1 ? dz - 1 : -dz) * B.dxf[2];
+        int lo = 1 << 20, hi = -(1 << 20);
+        for (int k = 0; k < ny; ++k) {
+            const int dy = mlo1 + k;
             const float ay = (float)(dy >= 1 ? dy - 1 : -dy) * B.dxf[1];
-            const float az = (float)(dz >= 1 ? dz - 1 : -dz) * B.dxf[2];
-            reach = fmaf(ay, ay, az * az) <= cut;
+            if (fmaf(ay, ay, az * az) <= cut) {
+                lo = min(lo, dy);
+                hi = max(hi, dy);
+            }
         }
-        const uint64_t mask = __ballot(reach);
-        const int lane = tid & 63, w = tid >> 6;
-        if (lane == 0) s_wcnt[w] = __popcll(mask);
-        __syncthreads();
-        int before = ncls, total = ncls;
-        for (int q = 0; q < kBlock / 64; ++q) {
-            before += (q < w) ? s_wcnt[q] : 0;
-            total += s_wcnt[q];
-        }
-        if (reach) {
-            // packed offsets (my + 512) | (mz + 512) << 10: no division per row
-            const int rank = __popcll(mask & ((1ull << lane) - 1ull));
-            s_cls[before + rank] = (mlo1 + k % ny + 512) | ((mlo2 + k / ny + 512) << 10);
-        }
-        ncls = total;
-        __syncthreads();
+        s_rng[tid] = lo <= hi ? ((lo + 512) | ((hi + 512) << 16)) : -1;
     }
+    __syncthreads();
     if (p >= B.np) return;
     const int64_t np = B.np;
     const int64_t slot = (n - M) % (M + 1);
@@ -266,19 +253,24 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
     }
     const int pid = (int)p;
     float Z = 0.0f;
-    for (int ci = 0; ci < ncls; ++ci) {
-        const int k = s_cls[ci];
-        const int my = (k & 1023) - 512, mz = (k >> 10) - 512;
-        const float ty = d1(my, phy, B.dxf[1]);
+    for (int iz = 0; iz < nz; ++iz) {
+        const int rg = s_rng[iz];
+        if (rg < 0) continue;
+        const int mz = mlo2 + iz;
         const float tz = d1(mz, phz, B.dxf[2]);
-        const float ryz = fmaf(ty, ty, tz * tz);
-        if (ryz > cut) continue;
-        int lo, hi;
-        row_range(phx, ryz, B, &B, slot, pid, my, mz, lo, hi);
-        if (lo > hi) continue;
-        // y-z factor of the row: raw v_exp_f32 of -ryz c (in [-R^2 c, 0])
-        Z = fmaf(__builtin_amdgcn_exp2f(-ryz * B.cexp),
-                 sP[hi - mlo0 + 1][tid] - sP[lo - mlo0][tid], Z);
+        const float tz2 = tz * tz;
+        const int ylo = (rg & 0xffff) - 512, yhi = (rg >> 16) - 512;
+        for (int my = ylo; my <= yhi; ++my) {
+            const float ty = d1(my, phy, B.dxf[1]);
+            const float ryz = fmaf(ty, ty, tz2);
+            if (ryz > cut) continue;
+            int lo, hi;
+            row_range(phx, ryz, B, &B, slot, pid, my, mz, lo, hi);
+            if (lo > hi) continue;
+            // y-z factor of the row: raw v_exp_f32 of -ryz c (in [-R^2 c, 0])
+            Z = fmaf(__builtin_amdgcn_exp2f(-ryz * B.cexp),
+                     sP[hi - mlo0 + 1][tid] - sP[lo - mlo0][tid], Z);
+        }
     }
     const float Zv = Z * (float)B.dV;
     const float inv = -B.rhof_inv / Zv;
