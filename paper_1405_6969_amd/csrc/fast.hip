@@ -599,18 +599,22 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
                     }
                 return q + o;
             };
-            int q = lane, nro = 0;
+            // lane l takes the items [l P, l P + P): the lanes of one pass are spread
+            // over the whole range, so fewer of them add into the same node or bank
+            const int P = (total + 63) >> 6;
+            int q = lane * P, nro = 0;
+            const int qend = min(q + P, total);
             float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na;
-            if (q < total) {
+            if (q < qend) {
                 const int g = record_of(q, nro);
                 na = rec[2 * (int64_t)g];
                 nb = rec[2 * (int64_t)g + 1];
             }
-            while (q < total) {
+            while (q < qend) {
                 const float4 qa = na, qb = nb;
                 const int ro = nro;
-                const int qn = q + 64;
-                if (qn < total) {
+                const int qn = q + 1;
+                if (qn < qend) {
                     const int g = record_of(qn, nro);
                     na = rec[2 * (int64_t)g];
                     nb = rec[2 * (int64_t)g + 1];
