@@ -436,6 +436,27 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
     /* Faxen correction of the drag (eq. force_particle, first line):
        (a_p^2/6) lap u~ with u~ = u - v_self */
     if (fax != 0.0) oracle_grid_laplacian(P, u, x, lu);
+    /* Heun: the second stage sits at x* = x^n + dt v^n, where the carrier, the
+       self term of the same injection (removed at each stage, Sec. 2.5) and the
+       Faxen Laplacians are evaluated again */
+    double *xs = NULL, *up2 = NULL, *vs2 = NULL, *lu2 = NULL, *ls2 = NULL;
+    if (P->integrator == 2) {
+        size_t sz = (size_t)(3 * np > 0 ? 3 * np : 1);
+        xs = (double *)malloc(sizeof(double) * sz);
+        up2 = (double *)malloc(sizeof(double) * sz);
+        vs2 = (double *)calloc(sz, sizeof(double));
+        lu2 = (double *)calloc(sz, sizeof(double));
+        ls2 = (double *)calloc(sz, sizeof(double));
+        for (p = 0; p < 3 * np; ++p) xs[p] = x[p] + P->dt * v[p];
+        oracle_gather(P, u, xs, up2);
+        if (P->self_correction && n >= M + 1) {
+            int64_t slot = (n - 1 - M) % (M + 1);
+            oracle_self_disturbance(P, xs, ring_x + slot * lvl, ring_d + slot * lvl, vs2);
+            if (fax != 0.0)
+                oracle_self_laplacian(P, xs, ring_x + slot * lvl, ring_d + slot * lvl, ls2);
+        }
+        if (fax != 0.0) oracle_grid_laplacian(P, u, xs, lu2);
+    }
     /* 3. carrier velocity at the particles */
     oracle_gather(P, u, x, up);
     /* 4. drag, history, explicit Euler */
@@ -465,6 +486,27 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
                 for (d = 0; d < 3; ++d) {
                     v[d * np + p] += P->dt * D[d] / P->m_p;
                     v[d * np + p] += P->dt * P->g[d];
+                }
+            } else if (P->integrator == 2) {
+                /* Heun: a_1 = (u~(x^n) - v^n)/tau + g, v* = v^n + dt a_1,
+                   a_2 = (u~(x*) - v*)/tau + g; v^{n+1} = v^n + dt (a_1 + a_2)/2,
+                   x^{n+1} = x^n + dt (v^n + v*)/2; the fluid gets the mean drag */
+                for (d = 0; d < 3; ++d) {
+                    double v0 = v[d * np + p];
+                    double ut1 = up[d * np + p] - vs[d * np + p];
+                    double ut2 = up2[d * np + p] - vs2[d * np + p];
+                    ut1 += fax * (lu[d * np + p] - ls[d * np + p]);
+                    ut2 += fax * (lu2[d * np + p] - ls2[d * np + p]);
+                    double d1 = (ut1 - v0) / t;
+                    double vst = v0 + P->dt * (d1 + P->g[d]);
+                    double d2 = (ut2 - vst) / t;
+                    double dm = 0.5 * (d1 + d2);
+                    D[d] = P->m_p * dm;
+                    hx[d * np + p] = x[d * np + p];
+                    hd[d * np + p] = D[d];
+                    if (dout) dout[d * np + p] = D[d];
+                    xn[d] = x[d * np + p] + 0.5 * P->dt * (v0 + vst);
+                    v[d * np + p] = v0 + P->dt * (dm + P->g[d]);
                 }
             } else {
                 /* dv/dt = (u~ - v)/tau + g with u~ held over the step has the
@@ -503,4 +545,9 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
     free(up);
     free(ls);
     free(lu);
+    free(xs);
+    free(up2);
+    free(vs2);
+    free(lu2);
+    free(ls2);
 }

@@ -37,7 +37,8 @@ typedef struct {
     double  dt;          /* time step */
     int32_t self_correction; /* 1: remove the closed-form self disturbance */
     double  g[3];        /* body acceleration of the particles, (m_p - m_f) g / m_p */
-    int32_t integrator;  /* 0 explicit Euler, 1 exact linear drag over the step */
+    int32_t integrator;  /* 0 explicit Euler, 1 exact linear drag over the step,
+                            2 Heun (two stages, self term removed at each) */
     double  a_p;         /* particle radius of the Faxen term (a_p^2/6) lap u~; 0 = off */
 } oracle_params;
 

@@ -413,6 +413,45 @@ def test_p10e_exponential_integrator_is_exact_for_a_uniform_carrier(dt_over_tau)
                        rtol=0, atol=1e-14)
 
 
+def test_p10h_heun_integrator_exact_discrete_solution_and_order():
+    """Heun (two stages) on a uniform carrier with a body force relaxes as
+    v^n = w + (v0 - w) q^n, q = 1 - h + h^2/2 (h = dt/tau), with
+    x^n = x0 + n dt w + dt (1 - h/2)(v0 - w)(1 - q^n)/(1 - q); its error against
+    the continuous solution (eq. uncoupled_solution with an initial slip) is
+    second order in dt.  The fluid receives the mean of the two stage drags."""
+    u0 = np.array([0.3, -0.2, 0.1])
+    gb = np.array([-0.9, 0.4, 2.0])
+    tau = 0.05
+    tau32 = float(np.float32(tau))
+    w = (u0 + tau32 * gb)[:, None]
+    errs = []
+    for dt in (4e-3, 2e-3, 1e-3):
+        n = int(round(0.1 / dt))
+        box = workloads.tiny_box(61, n=(16, 16, 16), np_=8, carrier="zero", tau=(tau,))
+        u = np.zeros_like(box.u) + u0[:, None, None, None]
+        P = _params(box, M=3, dt=dt, s=0)
+        P.g = (type(P.g))(*gb)
+        P.integrator = 2
+        run = oracle.Run(P, u, box.x, box.v, box.tau)
+        x0, v0 = box.x.copy(), box.v.copy()
+        for _ in range(n - 1):
+            run.step(want_f=False)
+        vb = run.v.copy()
+        _, D = run.step(want_f=False)
+        h = dt / tau32
+        q = 1 - h + h * h / 2
+        assert np.allclose(run.v, w + (v0 - w) * q ** n, rtol=1e-12, atol=1e-13)
+        x_ref = x0 + n * dt * w + dt * (1 - h / 2) * (v0 - w) * (1 - q ** n) / (1 - q)
+        dxw = run.x - x_ref
+        dxw -= box.L[0] * np.round(dxw / box.L[0])
+        assert np.max(np.abs(dxw)) < 1e-12
+        assert np.allclose(D * dt, box.m_p * (run.v - vb) - box.m_p * gb[:, None] * dt,
+                           rtol=0, atol=1e-14)
+        exact = w + (v0 - w) * math.exp(-n * dt / tau32)
+        errs.append(np.max(np.abs(run.v - exact)))
+    assert 3.6 < errs[0] / errs[1] < 4.4 and 3.6 < errs[1] / errs[2] < 4.4
+
+
 def test_p10_continuum_limit_uncoupled_solution():
     """As dt -> 0 the discrete relaxation converges to the paper's one-way
     solution v = v_t (1 - e^{-t/tau_p}) (eq. uncoupled_solution), here for a

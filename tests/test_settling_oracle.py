@@ -29,7 +29,7 @@ L = 2 * math.pi
 SIGMA = L / 16
 
 
-def settle(N, ratio, self_correction, sigma=SIGMA, T=6 * TAU):
+def settle(N, ratio, self_correction, sigma=SIGMA, T=6 * TAU, integrator=0):
     """Terminal-velocity error of the settling particle after T, against the
     discrete uncoupled solution v_t (1 - (1 - dt/tau)^K)."""
     dx = L / N
@@ -39,14 +39,16 @@ def settle(N, ratio, self_correction, sigma=SIGMA, T=6 * TAU):
     d = ratio * sigma
     m_p = 3 * math.pi * RHO * NU * d * TAU          # 6 pi mu a = m_p / tau_p
     P = oracle.make_params((N,) * 3, (L,) * 3, 1, m_p, RHO, NU, sigma, 3.0, 0.0, M, dt,
-                           self_correction, g=(G, 0.0, 0.0))
+                           self_correction, g=(G, 0.0, 0.0), integrator=integrator)
     x = np.array([[L / 2 + 0.3 * dx], [L / 2], [L / 2]])
     run = oracle.Run(P, np.zeros((3, N, N, N)), x, np.zeros((3, 1)), np.array([TAU], np.float32))
     for _ in range(K):
         f, _ = run.step(want_f=True)
         run.u = fluid.fluid_step((N,) * 3, (L,) * 3, NU, dt, run.u, f)
     tau32 = float(np.float32(TAU))
-    v_ref = tau32 * G * (1 - (1 - dt / tau32) ** K)
+    h = dt / tau32
+    q = 1 - h if integrator == 0 else 1 - h + h * h / 2
+    v_ref = tau32 * G * (1 - q ** K)
     return (run.v[0, 0] - run.u[0].mean()) / v_ref - 1.0, dt, m_p
 
 
@@ -71,3 +73,16 @@ def test_s3_grid_independent_at_fixed_sigma():
     e16, _, _ = settle(16, 0.25, 1)
     e32, _, _ = settle(32, 0.25, 1)
     assert abs(e16 - e32) < 5e-3
+
+
+def test_s4_heun_stages_with_self_removal():
+    """The paper extends the removal to each stage of a Runge-Kutta scheme
+    (Sec. 2.5).  With Heun and the removal at both stages the settling error
+    keeps the behaviour of the Euler scheme: first order in d_p / sigma_R, and
+    lower than without the removal."""
+    e1, _, _ = settle(16, 0.25, 1, integrator=2)
+    e2, _, _ = settle(16, 0.125, 1, integrator=2)
+    e_off, _, _ = settle(16, 0.25, 0, integrator=2)
+    assert 0.0 < e2 < e1 < 0.06
+    assert 1.9 < e1 / e2 < 2.1
+    assert e_off > e1
