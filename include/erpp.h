@@ -100,13 +100,20 @@ typedef enum {
     ERPP_EULER = 0,         /* explicit Euler (Sec. 2.5): D^n = m_p (u~ - v^n)/tau_p,
                                v^{n+1} = v^n + dt D^n/m_p + dt g_b,
                                x^{n+1} = x^n + dt v^n                              */
-    ERPP_EXPONENTIAL = 1    /* the linear drag ODE solved exactly over the step with
+    ERPP_EXPONENTIAL = 1,   /* the linear drag ODE solved exactly over the step with
                                u~ frozen: w = u~ + tau_p g_b,
                                v^{n+1} = w + (v^n - w) e^{-dt/tau_p},
                                x^{n+1} = x^n + dt w + tau_p (v^n - w)(1 - e^{-dt/tau_p});
                                drag handed to the fluid: the step average
                                m_p (v^{n+1} - v^n)/dt - m_p g_b.  Stable for any
                                dt/tau_p                                            */
+    ERPP_HEUN = 2           /* two-stage Runge-Kutta (Heun) with the App. E self term
+                               removed at each stage (Sec. 2.5): a_1 from u~(x^n),
+                               v* = v^n + dt a_1, a_2 from u~(x*) at
+                               x* = x^n + dt v^n, v^{n+1} = v^n + dt (a_1 + a_2)/2,
+                               x^{n+1} = x^n + dt (v^n + v*)/2; the fluid receives
+                               the mean of the two stage drags.  Boxes without
+                               mean shear only                                     */
 } erpp_integrator;
 
 typedef struct erpp_plan erpp_plan;   /* opaque: copies of the boxes, scratch,
@@ -152,9 +159,10 @@ erpp_status erpp_plan_set_faxen(erpp_plan *plan, int32_t ibox, double a_p);
 
 /* Particle integrator of every box (default ERPP_EULER).  The self-disturbance
  * removed from u~ is the same App. E closed form for both (the fluid receives
- * one forcing step of the handed-over drag either way).  Applies to later
- * steps and to captured graphs.  Synchronises the device.  ERPP_EINVAL for a
- * bad plan or kind. */
+ * one forcing step of the handed-over drag either way; Heun removes it at
+ * each stage's position).  Applies to later steps; invalidates captured graphs.
+ * Synchronises the device.  ERPP_EINVAL for a bad plan or kind, or Heun with a
+ * sheared box. */
 erpp_status erpp_plan_set_integrator(erpp_plan *plan, erpp_integrator kind);
 
 /* Autotuner (ERPP_F32_FAST): times every candidate pencil shape on the plan's own

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liberpp.so")
 
 ERPP_OK, ERPP_EINVAL, ERPP_ENOMEM, ERPP_EHIP, ERPP_EGEOM, ERPP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 F64_PLAIN, F32_FAST = 0, 1
-EULER, EXPONENTIAL = 0, 1
+EULER, EXPONENTIAL, HEUN = 0, 1, 2
 
 EXPORTS = ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile", "erpp_plan_tune",
            "erpp_plan_bins", "erpp_bin", "erpp_scatter", "erpp_gather", "erpp_step", "erpp_run",
@@ -212,7 +212,8 @@ class Plan:
         _check(self.lib.erpp_plan_set_faxen(self.h, int(ibox), float(a_p)), "erpp_plan_set_faxen")
 
     def set_integrator(self, kind: int):
-        """EULER (explicit Euler) or EXPONENTIAL (exact linear drag over the step)."""
+        """EULER (explicit Euler), EXPONENTIAL (exact linear drag over the step) or
+        HEUN (two stages, self term removed at each)."""
         _check(self.lib.erpp_plan_set_integrator(self.h, int(kind)), "erpp_plan_set_integrator")
 
     def get_tile(self):

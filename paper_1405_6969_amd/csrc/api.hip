@@ -448,9 +448,15 @@ erpp_status erpp_plan_set_faxen(erpp_plan *p, int32_t ibox, double a_p) {
 
 erpp_status erpp_plan_set_integrator(erpp_plan *p, erpp_integrator kind) {
     if (!p) return fail(ERPP_EINVAL, "plan is NULL");
-    if (kind != ERPP_EULER && kind != ERPP_EXPONENTIAL)
+    if (kind != ERPP_EULER && kind != ERPP_EXPONENTIAL && kind != ERPP_HEUN)
         return fail(ERPP_EINVAL, "unknown integrator %d", (int)kind);
+    if (kind == ERPP_HEUN)
+        for (int32_t b = 0; b < p->nbox; ++b)
+            if (p->boxes[b].shear != 0.0)
+                return fail(ERPP_EINVAL, "box %d: Heun needs shear = 0 (its second stage would "
+                                         "straddle the Lees-Edwards jump)", b);
     for (auto &B : p->hbox) B.integ = (int32_t)kind;
+    drop_graph(p);     // the update kernel's instance depends on it
     HIP_OR_RETURN(hipDeviceSynchronize());
     HIP_OR_RETURN(hipMemcpy(p->dbox, p->hbox.data(), sizeof(erpp::DevBox) * p->hbox.size(),
                             hipMemcpyHostToDevice));

@@ -290,7 +290,8 @@ __device__ __forceinline__ void self_laplacian64(const double r[3], const double
 // jump in y when a mean shear is present).  FP64.
 __device__ __forceinline__ void update_particle(const DevBox &B, int64_t p, double dt,
                                                 const double xp[3], const double up[3],
-                                                const double vs[3], double *hx, double *hdD,
+                                                const double vs[3], const double up2[3],
+                                                const double vs2[3], double *hx, double *hdD,
                                                 float *hdF) {
 #pragma clang fp contract(off)
     const int64_t np = B.np;
@@ -308,6 +309,22 @@ __device__ __forceinline__ void update_particle(const DevBox &B, int64_t p, doub
         for (int d = 0; d < 3; ++d) {
             vn[d] += dt * D[d] / B.m_p;
             vn[d] += dt * B.gb[d];
+        }
+    } else if (B.integ == 2) {
+        // Heun: stage 1 at (x^n, v^n), stage 2 at x* = x^n + dt v^n with
+        // v* = v^n + dt a_1 (carrier and self term evaluated there by the
+        // caller); the fluid gets the mean of the two stage drags
+        for (int d = 0; d < 3; ++d) {
+            const double v0 = B.v[d * np + p];
+            const double ut1 = up[d] - vs[d];
+            const double ut2 = up2[d] - vs2[d];
+            const double d1 = (ut1 - v0) / t;
+            const double vst = v0 + dt * (d1 + B.gb[d]);
+            const double d2 = (ut2 - vst) / t;
+            const double dm = 0.5 * (d1 + d2);
+            D[d] = B.m_p * dm;
+            xn[d] = xp[d] + 0.5 * dt * (v0 + vst);
+            vn[d] = v0 + dt * (dm + B.gb[d]);
         }
     } else {
         // exponential integrator: dv/dt = (u~ - v)/tau + g_b solved exactly over

@@ -718,9 +718,57 @@ __global__ void __launch_bounds__(kBlock) k_gather_sorted(const DevBox *__restri
     up[B.poff + r] = make_double4(u[0], u[1], u[2], 0.0);
 }
 
-// FAX: some box of the plan has a Faxen term (its extra work doubles the
-// registers, so plans without one run the lean instance)
+// Self term of particle p at position pos (the App. E disturbance of the last
+// injection, level n-1-M) into vs and, when FAX, the Faxen terms: up gets
+// fax lap u, vs gets fax lap v_self.
 template <bool FAX>
+__device__ __forceinline__ void self_terms(const DevBox &B, int64_t p, int64_t n, int M, int selfc,
+                                           const double pos[3], double up[3], double vs[3]) {
+    const int64_t np = B.np;
+    vs[0] = vs[1] = vs[2] = 0.0;
+    const bool live = selfc && n >= M + 1;
+    const int64_t ss = (n - 1 - M) % (M + 1);
+    const double *Xs = B.ring_x + ss * 3 * np;
+    const float *Ds = (const float *)B.ring_d + ss * 3 * np;
+    if (live) {
+        float r[3];
+        for (int d = 0; d < 3; ++d) {
+            double rd = pos[d] - Xs[d * np + p];
+            rd -= B.L[d] * rint(rd / B.L[d]);
+            r[d] = (float)rd;
+        }
+        float v0, v1, v2;
+        self_disturbance32(r[0], r[1], r[2], Ds[p], Ds[np + p], Ds[2 * np + p], B.s2sf,
+                           B.preff, v0, v1, v2);
+        vs[0] = v0;
+        vs[1] = v1;
+        vs[2] = v2;
+    }
+    if (FAX && B.fax != 0.0) {
+        // Faxen term (a_p^2/6) lap u~: grid Laplacian minus the self part
+        double lu[3], ls[3] = {0.0, 0.0, 0.0};
+        trilinear_laplacian<float>(B, (const float *)B.u, pos, lu);
+        if (live) {
+            double r[3], D[3];
+            for (int d = 0; d < 3; ++d) {
+                double rd = pos[d] - Xs[d * np + p];
+                rd -= B.L[d] * rint(rd / B.L[d]);
+                r[d] = rd;
+                D[d] = (double)Ds[d * np + p];
+            }
+            self_laplacian64(r, D, B.s2s, B.pref, ls);
+        }
+        for (int d = 0; d < 3; ++d) {
+            up[d] += B.fax * lu[d];
+            vs[d] += B.fax * ls[d];
+        }
+    }
+}
+
+// FAX: some box of the plan has a Faxen term; HEUN: some box uses the Heun
+// integrator (second stage at x* = x^n + dt v^n).  Their extra work doubles the
+// registers, so plans without them run the lean instance.
+template <bool FAX, bool HEUN>
 __global__ void __launch_bounds__(kBlock) k_update(const DevBox *__restrict__ Bs, int nbox,
                                                    const int64_t *__restrict__ stepp, int M,
                                                    double dt, int selfc,
@@ -743,48 +791,17 @@ __global__ void __launch_bounds__(kBlock) k_update(const DevBox *__restrict__ Bs
     } else {
         trilinear<float>(B, (const float *)B.u, xp, up);
     }
-    double vs[3] = {0.0, 0.0, 0.0};
-    if (selfc && n >= M + 1) {
-        const int64_t ss = (n - 1 - M) % (M + 1);
-        const double *Xs = B.ring_x + ss * 3 * np;
-        const float *Ds = (const float *)B.ring_d + ss * 3 * np;
-        float r[3];
-        for (int d = 0; d < 3; ++d) {
-            double rd = xp[d] - Xs[d * np + p];
-            rd -= B.L[d] * rint(rd / B.L[d]);
-            r[d] = (float)rd;
-        }
-        float v0, v1, v2;
-        self_disturbance32(r[0], r[1], r[2], Ds[p], Ds[np + p], Ds[2 * np + p], B.s2sf,
-                           B.preff, v0, v1, v2);
-        vs[0] = v0;
-        vs[1] = v1;
-        vs[2] = v2;
-    }
-    if (FAX && B.fax != 0.0) {
-        // Faxen term (a_p^2/6) lap u~: grid Laplacian minus the self part
-        double lu[3], ls[3] = {0.0, 0.0, 0.0};
-        trilinear_laplacian<float>(B, (const float *)B.u, xp, lu);
-        if (selfc && n >= M + 1) {
-            const int64_t ss = (n - 1 - M) % (M + 1);
-            const double *Xs = B.ring_x + ss * 3 * np;
-            const float *Ds = (const float *)B.ring_d + ss * 3 * np;
-            double r[3], D[3];
-            for (int d = 0; d < 3; ++d) {
-                double rd = xp[d] - Xs[d * np + p];
-                rd -= B.L[d] * rint(rd / B.L[d]);
-                r[d] = rd;
-                D[d] = (double)Ds[d * np + p];
-            }
-            self_laplacian64(r, D, B.s2s, B.pref, ls);
-        }
-        for (int d = 0; d < 3; ++d) {
-            up[d] += B.fax * lu[d];
-            vs[d] += B.fax * ls[d];
-        }
+    double vs[3];
+    self_terms<FAX>(B, p, n, M, selfc, xp, up, vs);
+    double up2[3] = {0.0, 0.0, 0.0}, vs2[3] = {0.0, 0.0, 0.0};
+    if (HEUN && B.integ == 2) {
+        const double xs[3] = {xp[0] + dt * B.v[p], xp[1] + dt * B.v[np + p],
+                              xp[2] + dt * B.v[2 * np + p]};
+        trilinear<float>(B, (const float *)B.u, xs, up2);
+        self_terms<FAX>(B, p, n, M, selfc, xs, up2, vs2);
     }
     const int64_t sw = n % (M + 1);
-    update_particle(B, p, dt, xp, up, vs, B.ring_x + sw * 3 * np, nullptr,
+    update_particle(B, p, dt, xp, up, vs, up2, vs2, B.ring_x + sw * 3 * np, nullptr,
                     (float *)B.ring_d + sw * 3 * np);
 }
 
@@ -911,9 +928,14 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                 hipLaunchKernelGGL(k_gather_sorted, dim3((unsigned)grid), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->pblocks, P->s.step + 1, P->M, P->s.xs,
                                    P->s.up);
-                bool fax = false;
-                for (const auto &B : P->hbox) fax = fax || B.fax != 0.0;
-                hipLaunchKernelGGL(fax ? k_update<true> : k_update<false>,
+                bool fax = false, heun = false;
+                for (const auto &B : P->hbox) {
+                    fax = fax || B.fax != 0.0;
+                    heun = heun || B.integ == 2;
+                }
+                auto upd = fax ? (heun ? k_update<true, true> : k_update<true, false>)
+                               : (heun ? k_update<false, true> : k_update<false, false>);
+                hipLaunchKernelGGL(upd,
                                    dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step + 1, P->M, P->dt, P->self_correction,
                                    P->s.up, P->s.sl);

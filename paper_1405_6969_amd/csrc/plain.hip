@@ -111,26 +111,21 @@ __global__ void __launch_bounds__(kBlock) k_plain_scatter(const DevBox *__restri
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_plain_update(const DevBox *__restrict__ Bs, int nbox,
-                                                         const int64_t *__restrict__ stepp, int M,
-                                                         double dt, int selfc) {
-    const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_p; });
-    const DevBox &B = Bs[bi];
-    const int64_t p = (int64_t)(blockIdx.x - B.blk_p) * kBlock + threadIdx.x;
-    if (p >= B.np) return;
-    const int64_t n = *stepp;
+// Carrier, self term and Faxen terms of particle p at position pos (FP64):
+// up = u(pos) + fax lap u(pos), vs = v_self(pos) + fax lap v_self(pos).
+__device__ __forceinline__ void plain_terms(const DevBox &B, int64_t p, int64_t n, int M,
+                                            int selfc, const double pos[3], double up[3],
+                                            double vs[3]) {
     const int64_t np = B.np;
-    double xp[3] = {B.x[p], B.x[np + p], B.x[2 * np + p]};
-    double up[3];
-    trilinear<double>(B, (const double *)B.u, xp, up);
-    double vs[3] = {0.0, 0.0, 0.0};
+    trilinear<double>(B, (const double *)B.u, pos, up);
+    vs[0] = vs[1] = vs[2] = 0.0;
     if (selfc && n >= M + 1) {
         const int64_t ss = (n - 1 - M) % (M + 1);
         const double *Xs = B.ring_x + ss * 3 * np;
         const double *Ds = (const double *)B.ring_d + ss * 3 * np;
         double r[3], D[3];
         for (int d = 0; d < 3; ++d) {
-            double rd = xp[d] - Xs[d * np + p];
+            double rd = pos[d] - Xs[d * np + p];
             rd -= B.L[d] * rint(rd / B.L[d]);
             r[d] = rd;
             D[d] = Ds[d * np + p];
@@ -145,11 +140,32 @@ __global__ void __launch_bounds__(kBlock) k_plain_update(const DevBox *__restric
     if (B.fax != 0.0) {
         // Faxen term (a_p^2/6) lap u~, grid part (the self part is above)
         double lu[3];
-        trilinear_laplacian<double>(B, (const double *)B.u, xp, lu);
+        trilinear_laplacian<double>(B, (const double *)B.u, pos, lu);
         for (int d = 0; d < 3; ++d) up[d] += B.fax * lu[d];
     }
+}
+
+__global__ void __launch_bounds__(kBlock) k_plain_update(const DevBox *__restrict__ Bs, int nbox,
+                                                         const int64_t *__restrict__ stepp, int M,
+                                                         double dt, int selfc) {
+    const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_p; });
+    const DevBox &B = Bs[bi];
+    const int64_t p = (int64_t)(blockIdx.x - B.blk_p) * kBlock + threadIdx.x;
+    if (p >= B.np) return;
+    const int64_t n = *stepp;
+    const int64_t np = B.np;
+    double xp[3] = {B.x[p], B.x[np + p], B.x[2 * np + p]};
+    double up[3], vs[3];
+    plain_terms(B, p, n, M, selfc, xp, up, vs);
+    double up2[3] = {0.0, 0.0, 0.0}, vs2[3] = {0.0, 0.0, 0.0};
+    if (B.integ == 2) {
+        // Heun's second stage at x* = x^n + dt v^n
+        const double xs[3] = {xp[0] + dt * B.v[p], xp[1] + dt * B.v[np + p],
+                              xp[2] + dt * B.v[2 * np + p]};
+        plain_terms(B, p, n, M, selfc, xs, up2, vs2);
+    }
     const int64_t sw = n % (M + 1);
-    update_particle(B, p, dt, xp, up, vs, B.ring_x + sw * 3 * np,
+    update_particle(B, p, dt, xp, up, vs, up2, vs2, B.ring_x + sw * 3 * np,
                     (double *)B.ring_d + sw * 3 * np, nullptr);
 }
 

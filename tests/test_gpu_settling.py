@@ -48,14 +48,21 @@ def _setup(N, sigma, ratio, prec, self_correction=1):
     return db, plan, fl, dt, m_p, x
 
 
-def _terminal_error(N, sigma, ratio, prec=erpp.F32_FAST, self_correction=1, T=6 * TAU):
+def _terminal_error(N, sigma, ratio, prec=erpp.F32_FAST, self_correction=1, T=6 * TAU,
+                    integrator=None):
     db, plan, fl, dt, _, _ = _setup(N, sigma, ratio, prec, self_correction)
     K = int(round(T / dt))
     with plan, fl:
+        if integrator is not None:
+            plan.set_integrator(integrator)
         plan.run_coupled([fl], 0, K, graph=True)
         torch.cuda.synchronize()
     tau32 = float(np.float32(TAU))
-    v_ref = tau32 * G * (1 - (1 - dt / tau32) ** K)
+    h = dt / tau32
+    # the discrete uncoupled solution of the scheme: amplification 1 - h (Euler),
+    # 1 - h + h^2/2 (Heun)
+    q = 1 - h + h * h / 2 if integrator == erpp.HEUN else 1 - h
+    v_ref = tau32 * G * (1 - q ** K)
     v = db.v[0, 0].item() - db.u[0].double().mean().item()
     return v / v_ref - 1.0
 
@@ -241,3 +248,80 @@ def test_faxen_term_matches_oracle(prec):
     tv, tu = (1e-12, 1e-12) if prec == erpp.F64_PLAIN else (1e-6, 1e-5)
     assert ev <= tv and eu <= tu
     assert effect > 100 * tv
+
+
+@pytest.mark.parametrize("prec", [erpp.F32_FAST, erpp.F64_PLAIN])
+@pytest.mark.parametrize("a_p_dx", [0.0, 0.6])
+def test_heun_integrator_matches_oracle(prec, a_p_dx):
+    """ERPP_HEUN (two stages, the self term removed at each, Sec. 2.5) in the
+    two-way coupled loop: k^-5/3 carrier, gravity, with and without the Faxen
+    correction (evaluated at both stages), 12 coupled steps against the
+    oracle's coupled loop with the same integrator.  Bars: v 1e-6 / 1e-12,
+    u 1e-5 / 1e-12; x within steps * dt * (v bar) * max|v| (FP32) and 1e-12
+    (FP64).  A graph captured under Euler must not be replayed afterwards."""
+    _cuda()
+    import workloads
+    from helpers import carrier_for, periodic_diff, upload
+    spec = workloads.BoxSpec(n=(32, 28, 24), L=(L, L * 28 / 32, L * 24 / 32), np_=1500,
+                             carrier="k53", kmax=8.0, tau=(0.02, 0.05), nu=0.05,
+                             mass_loading=1.0, placement="clustered", n_blobs=5,
+                             blob_radius_dx=3.0, seed=workloads.SEED_BASE + 123)
+    box = workloads.make_box(spec)
+    Mx, dt, steps = 3, 4e-3, 12
+    gb = (0.3, -1.0, 0.2)
+    a_p = a_p_dx * box.dx[0]
+    db = upload(box, Mx, prec)
+    with erpp.Plan([db], Mx, dt, precision=prec) as plan, \
+            erpp.Fluid(box.n, box.L, box.spec.nu, dt, precision=prec) as fl:
+        plan.set_body_force(0, gb)
+        plan.run_coupled([fl], 0, 0, graph=True)
+        plan.set_integrator(erpp.HEUN)
+        if a_p > 0:
+            plan.set_faxen(0, a_p)
+        plan.run_coupled([fl], 0, steps, graph=True)
+        torch.cuda.synchronize()
+        v, u, x = db.v.cpu().numpy(), db.u.double().cpu().numpy(), db.x.cpu().numpy()
+    P = oracle.params_for_box(box, Mx, dt, 1)
+    P.g = (type(P.g))(*gb)
+    P.integrator = 2
+    P.a_p = a_p
+    run = oracle.Run(P, carrier_for(box, prec), box.x, box.v, box.tau)
+    for _ in range(steps):
+        f, _ = run.step(want_f=True)
+        run.u = ofluid.fluid_step(box.n, box.L, box.spec.nu, dt, run.u, f)
+    ev, eu = rel_l2(v, run.v), rel_l2(u, run.u)
+    ex = np.max(np.abs(periodic_diff(x, run.x, box.L)))
+    print(f"prec {prec}, a_p/dx {a_p_dx}: Heun v {ev:.3e}, u {eu:.3e}, x {ex:.3e}")
+    tv, tu = (1e-12, 1e-12) if prec == erpp.F64_PLAIN else (1e-6, 1e-5)
+    assert ev <= tv and eu <= tu
+    assert ex <= (1e-12 if prec == erpp.F64_PLAIN else steps * dt * tv * np.max(np.abs(run.v)))
+
+
+def test_heun_settling_error_first_order():
+    """The settling particle with Heun and the stage-wise removal (24^3,
+    sigma_R = 2 pi / 24): the terminal-velocity error against the scheme's
+    discrete uncoupled solution is first order in d_p / sigma_R, and lower than
+    without the removal."""
+    _cuda()
+    sigma = L / 24
+    on = [_terminal_error(24, sigma, r, integrator=erpp.HEUN) for r in (0.25, 0.125)]
+    off = _terminal_error(24, sigma, 0.25, self_correction=0, integrator=erpp.HEUN)
+    print(f"Heun: error {on[0]:.4f}, {on[1]:.4f} at d_p/sigma_R 0.25, 0.125; "
+          f"{off:.4f} without removal")
+    assert 0.0 < on[1] < on[0] < 0.06
+    assert 1.8 < on[0] / on[1] < 2.2
+    assert off > on[0]
+
+
+def test_heun_rejects_sheared_box():
+    _cuda()
+    import workloads
+    from helpers import upload
+    spec = workloads.BoxSpec(n=(16, 16, 16), L=(L, L, L), np_=50, carrier="k53",
+                             kmax=4.0, tau=(0.05, 0.05), nu=0.05, mass_loading=0.1,
+                             placement="uniform", shear=1.0, seed=workloads.SEED_BASE + 5)
+    db = upload(workloads.make_box(spec), 2, erpp.F32_FAST)
+    with erpp.Plan([db], 2, 1e-3) as plan:
+        with pytest.raises(erpp.ErppError):
+            plan.set_integrator(erpp.HEUN)
+        plan.set_integrator(erpp.EXPONENTIAL)
