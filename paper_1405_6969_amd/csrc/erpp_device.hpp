@@ -46,7 +46,7 @@ __device__ __forceinline__ void cell_of(double x, double L, double dx, int N, in
 
 // Sphere membership of stencil node (mx,my,mz) in FP64, rounded exactly like the
 // definition: d = (m - phi) dx per dimension, r2 = dx^2 + dy^2 + dz^2 <= R2.
-__device__ __noinline__ bool inside64(int mx, int my, int mz, double phx, double phy,
+__device__ __forceinline__ bool inside64(int mx, int my, int mz, double phx, double phy,
                                       double phz, const DevBox &B) {
 #pragma clang fp contract(off)
     double ddx = ((double)mx - phx) * B.dx[0];
@@ -58,7 +58,7 @@ __device__ __noinline__ bool inside64(int mx, int my, int mz, double phx, double
 
 // Sphere membership decided in FP64 for a particle whose FP32 test fell inside
 // the guard band: re-read its delayed position from the ring (rare path).
-__device__ __noinline__ bool inside_exact(const DevBox *__restrict__ Bp, int64_t slot, int pid,
+__device__ __forceinline__ bool inside_exact(const DevBox *__restrict__ Bp, int64_t slot, int pid,
                                           int mx, int my, int mz) {
     const DevBox &B = *Bp;
     const int64_t np = B.np;
@@ -105,20 +105,37 @@ __device__ __forceinline__ bool inside32(int mx, float phx, float ryz, const Dev
 // end k: the end is k if k is inside, else the next node inward.  A row with
 // s < 0.01 can hold only the node nearest phi, which both ends then test.  The
 // node set is therefore the exact one, the same in every kernel that calls this.
-__device__ __forceinline__ void row_range(float phx, float ryz, const DevBox &B,
+// The box constants row_range reads, held by value so that a kernel can keep
+// them in registers across its loops.
+struct RowK {
+    float R2f, guard, idx0, dx0;
+    int mlo0, mhi0;
+};
+
+__device__ __forceinline__ RowK row_consts(const DevBox &B) {
+    return RowK{B.R2f, B.guard, B.idxf0, B.dxf[0], B.mlo[0], B.mhi[0]};
+}
+
+__device__ __forceinline__ void row_range(float phx, float ryz, const RowK &K,
                                           const DevBox *Bp, int64_t slot, int pid, int my,
                                           int mz, int &lo, int &hi) {
-    const float rem = fmaxf(B.R2f - ryz, 0.0f);
-    const float s = __builtin_amdgcn_sqrtf(rem) * B.idxf0;
+    const float rem = fmaxf(K.R2f - ryz, 0.0f);
+    const float s = __builtin_amdgcn_sqrtf(rem) * K.idx0;
     const float kl = rintf(phx - s), kh = rintf(phx + s);
-    const float tl = (kl - phx) * B.dxf[0], th = (kh - phx) * B.dxf[0];
+    const float tl = (kl - phx) * K.dx0, th = (kh - phx) * K.dx0;
     const float dl = fmaf(tl, tl, ryz), dh = fmaf(th, th, ryz);
-    const float below = B.R2f - B.guard, above = B.R2f + B.guard;
+    const float below = K.R2f - K.guard, above = K.R2f + K.guard;
     bool il = dl < below, ih = dh < below;
     if (dl >= below && dl <= above) il = inside_exact(Bp, slot, pid, (int)kl, my, mz);
     if (dh >= below && dh <= above) ih = inside_exact(Bp, slot, pid, (int)kh, my, mz);
-    lo = max((int)kl + (il ? 0 : 1), B.mlo[0]);
-    hi = min((int)kh - (ih ? 0 : 1), B.mhi[0]);
+    lo = max((int)kl + (il ? 0 : 1), K.mlo0);
+    hi = min((int)kh - (ih ? 0 : 1), K.mhi0);
+}
+
+__device__ __forceinline__ void row_range(float phx, float ryz, const DevBox &B,
+                                          const DevBox *Bp, int64_t slot, int pid, int my,
+                                          int mz, int &lo, int &hi) {
+    row_range(phx, ryz, row_consts(B), Bp, slot, pid, my, mz, lo, hi);
 }
 
 // ---------------------------------------------------------- self-disturbance --

@@ -440,6 +440,12 @@ __global__ void __launch_bounds__(kBlock) k_pencil_scale(const DevBox *__restric
 
 // --------------------------------------------------------------- scatter ----
 
+// Makes the four values available in registers at this point (the compiler
+// places the wait for their load here); emits no instruction.
+__device__ __forceinline__ void pin4(float4 &v) {
+    asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
+}
+
 // Contribution to the integer tile: v_cvt_rpi_i32_f32 rounds to floor(v + 0.5)
 // in one instruction (|v| < 2^30 by the choice of scale; the error of one term
 // is at most half a unit; ties, which round up, have measure zero).
@@ -552,9 +558,17 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
         // fixed-point scale of the pencil (k_pencil_scale)
         scale = pscale[blockIdx.x];
         const int64_t slot = (n - M) % (M + 1);
-        const float hx = B.dxf[0], hy = B.dxf[1], hz = B.dxf[2];
-        const float c = B.cexp;
+        float hx = B.dxf[0], hy = B.dxf[1], hz = B.dxf[2];
+        float c = B.cexp;
         const float qx = exp2f(-2.0f * c * hx * hx);
+        // box constants of the row loop, pinned in registers: reloading them from
+        // the box descriptor inside the loop would wait on the LDS counter, i.e.
+        // on the previous row's atomics
+        RowK K = row_consts(B);
+        float cutv = cut;
+        asm volatile("" : "+v"(K.R2f), "+v"(K.guard), "+v"(K.idx0), "+v"(K.dx0));
+        asm volatile("" : "+v"(K.mlo0), "+v"(K.mhi0), "+v"(hx), "+v"(hy), "+v"(hz), "+v"(c),
+                     "+v"(cutv));
         const int ncls = s_ncls;
         const int nr = 2 * e2;
         for (int ci = wv; ci < ncls; ci += NT / 64) {
@@ -602,34 +616,20 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
             // lane l takes the items [l P, l P + P): the lanes of one pass are spread
             // over the whole range, so fewer of them add into the same node or bank
             const int P = (total + 63) >> 6;
-            int q = lane * P, nro = 0;
+            int q = lane * P;
             const int qend = min(q + P, total);
-            float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na;
-            if (q < qend) {
-                const int g = record_of(q, nro);
-                na = rec[2 * (int64_t)g];
-                nb = rec[2 * (int64_t)g + 1];
-            }
-            while (q < qend) {
-                const float4 qa = na, qb = nb;
-                const int ro = nro;
-                const int qn = q + 1;
-                if (qn < qend) {
-                    const int g = record_of(qn, nro);
-                    na = rec[2 * (int64_t)g];
-                    nb = rec[2 * (int64_t)g + 1];
-                }
-                q = qn;
+            // one stencil row: range, first weight, then the node walk
+            auto row = [&](const float4 qa, const float4 qb, const int ro) {
                 const uint32_t ijk = __float_as_uint(qa.w);
                 const int b0 = (int)(ijk & 2047u);
                 const int b1 = (int)((ijk >> 11) & 2047u);
                 const float tyv = d1(dy, qa.y, hy);
                 const float tzv = d1(dz, qa.z, hz);
                 const float ryz = fmaf(tyv, tyv, tzv * tzv);
-                if (ryz > cut) continue;
+                if (ryz > cutv) return;
                 int rlo, rhi;
-                row_range(qa.x, ryz, B, &B, slot, __float_as_int(qb.w), dy, dz, rlo, rhi);
-                if (rlo > rhi) continue;
+                row_range(qa.x, ryz, K, &B, slot, __float_as_int(qb.w), dy, dz, rlo, rhi);
+                if (rlo > rhi) return;
                 // raw v_exp_f32: both arguments lie in [-2 R^2 c, 0], far from underflow
                 const float t0 = ((float)rlo - qa.x) * hx;
                 float w = __builtin_amdgcn_exp2f(-fmaf(t0, t0, ryz) * c);
@@ -651,6 +651,38 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
                     rr *= qx;
                     ap += 3;
                 } while (ap != ae);
+            };
+            // records are fetched one item ahead into two register sets used in
+            // turn (no copies between them).  The fetch is unconditional (the last
+            // item re-reads its own record) and each set is pinned before the next
+            // fetch is issued, so the wait for a set never waits for the younger
+            // fetch behind it.
+            float4 ra0, rb0, ra1, rb1;
+            int ro0 = 0, ro1 = 0;
+            if (q < qend) {
+                const int g = record_of(q, ro0);
+                ra0 = rec[2 * (int64_t)g];
+                rb0 = rec[2 * (int64_t)g + 1];
+            }
+            while (q < qend) {
+                pin4(ra0);
+                pin4(rb0);
+                {
+                    const int g = record_of(min(q + 1, qend - 1), ro1);
+                    ra1 = rec[2 * (int64_t)g];
+                    rb1 = rec[2 * (int64_t)g + 1];
+                }
+                row(ra0, rb0, ro0);
+                if (++q >= qend) break;
+                pin4(ra1);
+                pin4(rb1);
+                {
+                    const int g = record_of(min(q + 1, qend - 1), ro0);
+                    ra0 = rec[2 * (int64_t)g];
+                    rb0 = rec[2 * (int64_t)g + 1];
+                }
+                row(ra1, rb1, ro1);
+                ++q;
             }
         }
     }
