@@ -36,7 +36,8 @@ class Params(C.Structure):
                 ("m_p", C.c_double), ("rho_f", C.c_double), ("nu", C.c_double),
                 ("sigma", C.c_double), ("cutoff", C.c_double), ("shear", C.c_double),
                 ("M", C.c_int32), ("dt", C.c_double), ("self_correction", C.c_int32),
-                ("g", C.c_double * 3), ("integrator", C.c_int32), ("a_p", C.c_double)]
+                ("g", C.c_double * 3), ("integrator", C.c_int32), ("a_p", C.c_double),
+                ("a_am", C.c_double)]
 
 
 _lib = None
@@ -57,12 +58,15 @@ def _load():
         lib.oracle_normalisation.argtypes = [P, d, d]
         lib.oracle_self_disturbance.argtypes = [P, d, d, d, d]
         lib.oracle_gather.argtypes = [P, d, d, d]
-        lib.oracle_step.argtypes = [P, C.c_int64, d, d, d, f32, d, d, i32, i32, d, d]
+        lib.oracle_step.argtypes = [P, C.c_int64, d, d, d, f32, d, d, i32, i32, d, d, d, i32]
+        lib.oracle_self_gradient.argtypes = [P, d, d, d, d]
+        lib.oracle_grid_gradient.argtypes = [P, d, d, d]
         lib.oracle_self_laplacian.argtypes = [P, d, d, d, d]
         lib.oracle_grid_laplacian.argtypes = [P, d, d, d]
         for fn in (lib.oracle_bin, lib.oracle_deposit, lib.oracle_normalisation,
                    lib.oracle_self_disturbance, lib.oracle_gather, lib.oracle_step,
-                   lib.oracle_self_laplacian, lib.oracle_grid_laplacian):
+                   lib.oracle_self_laplacian, lib.oracle_grid_laplacian,
+                   lib.oracle_self_gradient, lib.oracle_grid_gradient):
             fn.restype = None
         _lib = lib
     return _lib
@@ -78,7 +82,7 @@ def _f64(a):
 
 def make_params(n, L, np_, m_p, rho_f, nu, sigma, cutoff=3.0, shear=0.0, M=1,
                 dt=1e-3, self_correction=1, g=(0.0, 0.0, 0.0), integrator=0,
-                a_p=0.0) -> Params:
+                a_p=0.0, a_am=0.0) -> Params:
     P = Params()
     P.n = (C.c_int32 * 3)(*[int(v) for v in n])
     P.L = (C.c_double * 3)(*[float(v) for v in L])
@@ -89,6 +93,10 @@ def make_params(n, L, np_, m_p, rho_f, nu, sigma, cutoff=3.0, shear=0.0, M=1,
     P.g = (C.c_double * 3)(*[float(a) for a in g])
     P.integrator = int(integrator)
     P.a_p = float(a_p)
+    P.a_am = float(a_am)
+    if P.a_am > 0.0 and (P.integrator != 0 or P.shear != 0.0):
+        raise ValueError("added mass is defined for the explicit Euler integrator in a "
+                         "box without mean shear")
     for d in range(3):
         dxd = P.L[d] / P.n[d]
         R = int(np.ceil(P.cutoff * P.sigma / dxd))
@@ -176,6 +184,27 @@ def self_laplacian(P: Params, x, Xp, Dp):
     return ls
 
 
+def self_gradient(P: Params, x, Xp, Dp):
+    """Gradient of the closed-form self-disturbance, [3 (component)][3 (direction)][np]."""
+    x, Xp, Dp = _f64(x), _f64(Xp), _f64(Dp)
+    Q = _with_np(P, x.shape[1])
+    gs = np.empty((3, 3, x.shape[1]))
+    _load().oracle_self_gradient(C.byref(Q), _ptr(x, C.c_double), _ptr(Xp, C.c_double),
+                                 _ptr(Dp, C.c_double), _ptr(gs, C.c_double))
+    return gs
+
+
+def grid_gradient(P: Params, u, x):
+    """Trilinear interpolation of the central-difference nodal gradient of u (plus the
+    mean shear), [3 (component)][3 (direction)][np]."""
+    u, x = _f64(u), _f64(x)
+    Q = _with_np(P, x.shape[1])
+    gu = np.empty((3, 3, x.shape[1]))
+    _load().oracle_grid_gradient(C.byref(Q), _ptr(u, C.c_double), _ptr(x, C.c_double),
+                                 _ptr(gu, C.c_double))
+    return gu
+
+
 def grid_laplacian(P: Params, u, x):
     """Trilinear interpolation of the 7-point nodal Laplacian of u at x."""
     u, x = _f64(u), _f64(x)
@@ -208,6 +237,9 @@ class Run:
         self.P = _with_np(P, np_)
         self.ring_x = np.zeros((P.M + 1, 3, np_))
         self.ring_d = np.zeros((P.M + 1, 3, np_))
+        # added-mass history: u~ and u~ + (a^2/10) lap u~ of the previous step
+        self.am_hist = np.zeros((6, np_))
+        self.am_valid = np.zeros(1, np.int32)
         self.n = 0
 
     def step(self, want_f=True, lo=None, wn=None):
@@ -221,6 +253,7 @@ class Run:
                             _ptr(self.x, C.c_double), _ptr(self.v, C.c_double),
                             _ptr(self.tau, C.c_float), _ptr(self.ring_x, C.c_double),
                             _ptr(self.ring_d, C.c_double), _ptr(lo_a, C.c_int32),
-                            _ptr(wn_a, C.c_int32), fp, _ptr(D, C.c_double))
+                            _ptr(wn_a, C.c_int32), fp, _ptr(D, C.c_double),
+                            _ptr(self.am_hist, C.c_double), _ptr(self.am_valid, C.c_int32))
         self.n += 1
         return f, D

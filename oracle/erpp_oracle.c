@@ -323,6 +323,117 @@ void oracle_self_laplacian(const oracle_params *P, const double *x,
     }
 }
 
+/* Gradient of the App. E disturbance.  With v_c = pref [A D_c - (D.r) r_c H],
+ * A = e^{-eta^2} - F and H = (e^{-eta^2} - 3F) / r^2 (both functions of r^2
+ * through eta^2 = r^2 / (2 s), s = sigma_s^2), the derivatives
+ *   dF/d(eta^2) = (e^{-eta^2} - 3F) / (2 eta^2)   (from f'(eta) = 2 eta^2 e^{-eta^2})
+ *   dA/d(r^2)   = -(e^{-eta^2}/s + H) / 2
+ *   dH/d(r^2)   = -K / 2,  K = (e^{-eta^2}/s + 5H) / r^2
+ * give
+ *   d_j v_c = pref [ -(e/s + H) r_j D_c - H D_j r_c - H (D.r) delta_cj + K (D.r) r_c r_j ].
+ * K is finite at r = 0; for eta < 0.3 it is summed from its Maclaurin series
+ *   K = (1 / (2 s^2)) sum_{m>=1} (-1)^m 2m eta^{2(m-1)} / (m! (2m + 5)).
+ * (The trace vanishes: the disturbance is solenoidal.) */
+static void self_gradient_one(const oracle_params *P, const double r[3],
+                              const double Dp[3], double gs[9])
+{
+    const double s2 = P->sigma * P->sigma + 2.0 * P->nu * P->dt;
+    const double pref = -(P->dt / P->rho_f) * pow(2.0 * ORACLE_PI * s2, -1.5);
+    const double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const double eta2 = rr / (2.0 * s2);
+    const double eta = sqrt(eta2);
+    const double e = exp(-eta2);
+    const double Dr = Dp[0] * r[0] + Dp[1] * r[1] + Dp[2] * r[2];
+    double H, K;
+    int c, j;
+    if (eta < 0.3) {
+        double q = -1.0; /* (-1)^m eta^{2(m-1)} / m!, m >= 1 */
+        int m;
+        H = 0.0;
+        K = 0.0;
+        for (m = 1; m <= 8; ++m) {
+            H += (2.0 * m) * q / (2.0 * m + 3.0);
+            K += (2.0 * m) * q / (2.0 * m + 5.0);
+            q *= -eta2 / (double)(m + 1);
+        }
+        H /= 2.0 * s2;
+        K /= 2.0 * s2 * s2;
+    } else {
+        const double fe = 0.5 * sqrt(ORACLE_PI) * erf(eta) - eta * e;
+        const double F = fe / (2.0 * eta * eta2);
+        H = (e - 3.0 * F) / rr;
+        K = (e / s2 + 5.0 * H) / rr;
+    }
+    for (c = 0; c < 3; ++c)
+        for (j = 0; j < 3; ++j) {
+            double t = -(e / s2 + H) * r[j] * Dp[c] - H * Dp[j] * r[c] + K * Dr * r[c] * r[j];
+            if (c == j) t -= H * Dr;
+            gs[3 * c + j] = pref * t;
+        }
+}
+
+void oracle_self_gradient(const oracle_params *P, const double *x,
+                          const double *Xp, const double *Dp, double *gs)
+{
+    const int64_t np = P->np;
+    int64_t p;
+    for (p = 0; p < np; ++p) {
+        double r[3], D[3], out[9];
+        int d;
+        for (d = 0; d < 3; ++d) {
+            double rd = x[d * np + p] - Xp[d * np + p];
+            rd -= P->L[d] * nearbyint(rd / P->L[d]);
+            r[d] = rd;
+            D[d] = Dp[d * np + p];
+        }
+        self_gradient_one(P, r, D, out);
+        for (d = 0; d < 9; ++d) gs[d * np + p] = out[d];
+    }
+}
+
+/* Central difference d u_c / d x_j at node (i, j, k), periodic. */
+static double node_derivative(const oracle_params *P, const double *u, int c, int dir,
+                              int64_t i, int64_t j, int64_t k)
+{
+    const int64_t Nx = P->n[0], Ny = P->n[1], Nz = P->n[2];
+    const double *uc = u + (int64_t)c * Nx * Ny * Nz;
+    const double h = P->L[dir] / P->n[dir];
+    const int64_t di = dir == 0, dj = dir == 1, dk = dir == 2;
+#define U_AT(a, b, d) uc[(imod(d, Nz) * Ny + imod(b, Ny)) * Nx + imod(a, Nx)]
+    const double up = U_AT(i + di, j + dj, k + dk), um = U_AT(i - di, j - dj, k - dk);
+#undef U_AT
+    return (up - um) / (2.0 * h);
+}
+
+void oracle_grid_gradient(const oracle_params *P, const double *u, const double *x,
+                          double *gu)
+{
+    const int64_t np = P->np;
+    int64_t p;
+    for (p = 0; p < np; ++p) {
+        int32_t b[3];
+        double phi[3], w[3][2], acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        int d, a, bb, cc, c, j;
+        for (d = 0; d < 3; ++d) {
+            cell_of(x[d * np + p], P->L[d], P->n[d], &b[d], &phi[d]);
+            w[d][0] = 1.0 - phi[d];
+            w[d][1] = phi[d];
+        }
+        for (cc = 0; cc < 2; ++cc)
+            for (bb = 0; bb < 2; ++bb)
+                for (a = 0; a < 2; ++a) {
+                    double wt = w[0][a] * w[1][bb] * w[2][cc];
+                    for (c = 0; c < 3; ++c)
+                        for (j = 0; j < 3; ++j)
+                            acc[3 * c + j] += wt * node_derivative(P, u, c, j, (int64_t)b[0] + a,
+                                                                   (int64_t)b[1] + bb,
+                                                                   (int64_t)b[2] + cc);
+                }
+        acc[1] += P->shear; /* d U_x / d y of the mean shear */
+        for (d = 0; d < 9; ++d) gu[d * np + p] = acc[d];
+    }
+}
+
 /* 7-point Laplacian of component c at node (i, j, k), periodic. */
 static double node_laplacian(const oracle_params *P, const double *u, int c, int64_t i,
                              int64_t j, int64_t k)
@@ -404,7 +515,7 @@ void oracle_gather(const oracle_params *P, const double *u, const double *x,
 void oracle_step(const oracle_params *P, int64_t n, const double *u,
                  double *x, double *v, const float *tau, double *ring_x,
                  double *ring_d, const int32_t lo[3], const int32_t wn[3],
-                 double *f, double *dout)
+                 double *f, double *dout, double *am_hist, int32_t *am_valid)
 {
     const int64_t np = P->np;
     const int32_t M = P->M;
@@ -414,6 +525,11 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
     double *ls = (double *)calloc((size_t)(3 * np > 0 ? 3 * np : 1), sizeof(double));
     double *lu = (double *)calloc((size_t)(3 * np > 0 ? 3 * np : 1), sizeof(double));
     const double fax = P->a_p * P->a_p / 6.0;
+    /* added mass (eq. force_particle, second line): displaced mass and the
+       Faxen coefficient of its d/dt term */
+    const int am = P->a_am > 0.0;
+    const double m_f = am ? P->rho_f * 4.0 / 3.0 * ORACLE_PI * P->a_am * P->a_am * P->a_am : 0.0;
+    const double fam = P->a_am * P->a_am / 10.0;
     int64_t p;
 
     /* 1. forcing from the drag delayed by eps_R = M dt */
@@ -430,12 +546,25 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
     if (P->self_correction && n >= M + 1) {
         int64_t slot = (n - 1 - M) % (M + 1);
         oracle_self_disturbance(P, x, ring_x + slot * lvl, ring_d + slot * lvl, vs);
-        if (fax != 0.0)
+        if (fax != 0.0 || am)
             oracle_self_laplacian(P, x, ring_x + slot * lvl, ring_d + slot * lvl, ls);
     }
     /* Faxen correction of the drag (eq. force_particle, first line):
        (a_p^2/6) lap u~ with u~ = u - v_self */
-    if (fax != 0.0) oracle_grid_laplacian(P, u, x, lu);
+    if (fax != 0.0 || am) oracle_grid_laplacian(P, u, x, lu);
+    /* added mass: the gradient of u~ = u - v_self for the convective part of
+       the fluid acceleration */
+    double *gu = NULL, *gs = NULL;
+    if (am) {
+        size_t sz = (size_t)(9 * np > 0 ? 9 * np : 1);
+        gu = (double *)malloc(sizeof(double) * sz);
+        gs = (double *)calloc(sz, sizeof(double));
+        oracle_grid_gradient(P, u, x, gu);
+        if (P->self_correction && n >= M + 1) {
+            int64_t slot = (n - 1 - M) % (M + 1);
+            oracle_self_gradient(P, x, ring_x + slot * lvl, ring_d + slot * lvl, gs);
+        }
+    }
     /* Heun: the second stage sits at x* = x^n + dt v^n, where the carrier, the
        self term of the same injection (removed at each stage, Sec. 2.5) and the
        Faxen Laplacians are evaluated again */
@@ -469,7 +598,48 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
             double D[3], xn[3];
             int d;
             int64_t k;
-            if (P->integrator == 0) {
+            if (am) {
+                /* eq. force_particle, first two lines, explicit Euler with the
+                   particle's own acceleration moved to the left:
+                     (m_p + m_f/2) dv/dt = S + m_f Du~/Dt + (m_f/2) dq/dt + m_p g_b,
+                   S = m_p (u~ + (a_p^2/6) lap u~ - v) / tau_p,
+                   q = u~ + (a_am^2/10) lap u~,
+                   d/dt along the path: (value^n - value^{n-1}) / dt (zero on the
+                   first step, which has no previous value),
+                   Du~/Dt = du~/dt + (u~ - v) . grad u~ (material derivative from
+                   the path derivative).  D = m_p dv/dt - m_p g_b is the
+                   hydrodynamic force handed to the fluid. */
+                double ut[3], q[3], S[3], Dm[3], acc[3];
+                const int valid = *am_valid;
+                for (d = 0; d < 3; ++d) {
+                    ut[d] = up[d * np + p] - vs[d * np + p];
+                    q[d] = ut[d] + fam * (lu[d * np + p] - ls[d * np + p]);
+                    S[d] = P->m_p * (ut[d] + fax * (lu[d * np + p] - ls[d * np + p]) -
+                                     v[d * np + p]) / t;
+                }
+                for (d = 0; d < 3; ++d) {
+                    double conv = 0.0;
+                    int jd;
+                    for (jd = 0; jd < 3; ++jd)
+                        conv += (ut[jd] - v[jd * np + p]) *
+                                (gu[(3 * d + jd) * np + p] - gs[(3 * d + jd) * np + p]);
+                    double dut = valid ? (ut[d] - am_hist[d * np + p]) / P->dt : 0.0;
+                    double dq = valid ? (q[d] - am_hist[(3 + d) * np + p]) / P->dt : 0.0;
+                    Dm[d] = dut + conv;
+                    acc[d] = (S[d] + m_f * Dm[d] + 0.5 * m_f * dq + P->m_p * P->g[d]) /
+                             (P->m_p + 0.5 * m_f);
+                    D[d] = S[d] + m_f * Dm[d] + 0.5 * m_f * (dq - acc[d]);
+                }
+                for (d = 0; d < 3; ++d) {
+                    hx[d * np + p] = x[d * np + p];
+                    hd[d * np + p] = D[d];
+                    if (dout) dout[d * np + p] = D[d];
+                    xn[d] = x[d * np + p] + P->dt * v[d * np + p];
+                    v[d * np + p] += P->dt * acc[d];
+                    am_hist[d * np + p] = ut[d];
+                    am_hist[(3 + d) * np + p] = q[d];
+                }
+            } else if (P->integrator == 0) {
                 for (d = 0; d < 3; ++d) {
                     double ut = up[d * np + p] - vs[d * np + p];
                     ut += fax * (lu[d * np + p] - ls[d * np + p]);
@@ -541,6 +711,9 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
             }
         }
     }
+    if (am) *am_valid = 1;
+    free(gu);
+    free(gs);
     free(vs);
     free(up);
     free(ls);

@@ -40,6 +40,8 @@ typedef struct {
     int32_t integrator;  /* 0 explicit Euler, 1 exact linear drag over the step,
                             2 Heun (two stages, self term removed at each) */
     double  a_p;         /* particle radius of the Faxen term (a_p^2/6) lap u~; 0 = off */
+    double  a_am;        /* particle radius of the added-mass terms (displaced mass
+                            m_f = rho_f 4/3 pi a_am^3, Faxen part a_am^2/10); 0 = off */
 } oracle_params;
 
 /* Cell key of each position and a stable counting sort by key.
@@ -66,6 +68,16 @@ void oracle_self_disturbance(const oracle_params *P, const double *x,
 void oracle_self_laplacian(const oracle_params *P, const double *x,
                            const double *Xp, const double *Dp, double *ls);
 
+/* Gradient of the closed-form self-disturbance at x (same arguments as
+ * oracle_self_disturbance): gs[(3 c + j) np + p] = d v_c / d x_j. */
+void oracle_self_gradient(const oracle_params *P, const double *x,
+                          const double *Xp, const double *Dp, double *gs);
+
+/* Trilinear interpolation at x of the central-difference nodal gradient of u,
+ * plus the mean shear's d U_x / d y = S: gu[(3 c + j) np + p] = d u_c / d x_j. */
+void oracle_grid_gradient(const oracle_params *P, const double *u, const double *x,
+                          double *gu);
+
 /* Trilinear interpolation at x of the 7-point nodal Laplacian of u. */
 void oracle_grid_laplacian(const oracle_params *P, const double *u, const double *x,
                            double *lu);
@@ -76,11 +88,14 @@ void oracle_gather(const oracle_params *P, const double *u, const double *x,
 
 /* One coupling step n: forcing f (on the window, NULL to skip), drag D^n into
  * ring slot n mod (M+1), and x^n, v^n -> x^{n+1}, v^{n+1} in place.
- * dout (optional, [3][np]) receives D^n. */
+ * dout (optional, [3][np]) receives D^n.  With a_am > 0, am_hist ([6][np]:
+ * u~ and u~ + (a_am^2/10) lap u~ of the previous step) and *am_valid (0 before
+ * the first step with added mass) carry the added-mass history; otherwise both
+ * may be NULL. */
 void oracle_step(const oracle_params *P, int64_t n, const double *u,
                  double *x, double *v, const float *tau, double *ring_x,
                  double *ring_d, const int32_t lo[3], const int32_t wn[3],
-                 double *f, double *dout);
+                 double *f, double *dout, double *am_hist, int32_t *am_valid);
 
 #ifdef __cplusplus
 }

@@ -242,34 +242,51 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
     const float D0 = Dd[p], D1 = Dd[np + p], D2 = Dd[2 * np + p];
     const double x0 = B.x[p], x1 = B.x[np + p], x2 = B.x[2 * np + p];
     const int mlo0 = B.mlo[0], mhi0 = B.mhi[0];
-    // prefix sums of the x factors (indexed by the row ends)
+    float hx = B.dxf[0], hy = B.dxf[1], hz = B.dxf[2], c = B.cexp;
+    // box constants of the row loop, pinned in registers (a reload from the box
+    // descriptor inside the loop would wait on the LDS counter)
+    RowK K = row_consts(B);
+    float cutv = cut;
+    asm volatile("" : "+v"(K.R2f), "+v"(K.guard), "+v"(K.idx0), "+v"(K.dx0));
+    asm volatile("" : "+v"(K.mlo0), "+v"(K.mhi0), "+v"(hx), "+v"(hy), "+v"(hz), "+v"(c),
+                 "+v"(cutv));
+    // prefix sums of the x factors (indexed by the row ends); raw v_exp_f32, the
+    // arguments lie in [-(R + dx)^2 c, 0]
     sP[0][tid] = 0.0f;
     {
         float acc = 0.0f;
         for (int m = mlo0; m <= mhi0; ++m) {
-            acc += g1(m, phx, B.dxf[0], B.cexp);
+            const float t = ((float)m - phx) * hx;
+            acc += __builtin_amdgcn_exp2f(-(t * t) * c);
             sP[m - mlo0 + 1][tid] = acc;
         }
     }
     const int pid = (int)p;
+    // y factor of row my by the ratio recurrence along y: gy(my + 1) = gy(my) r(my),
+    // r(my + 1) = r(my) qy, with r(my) = exp2(-c hy^2 (2 (my - phy) + 1))
+    const float qy = __builtin_amdgcn_exp2f(-2.0f * c * hy * hy);
     float Z = 0.0f;
     for (int iz = 0; iz < nz; ++iz) {
         const int rg = s_rng[iz];
         if (rg < 0) continue;
         const int mz = mlo2 + iz;
-        const float tz = d1(mz, phz, B.dxf[2]);
+        const float tz = d1(mz, phz, hz);
         const float tz2 = tz * tz;
         const int ylo = (rg & 0xffff) - 512, yhi = (rg >> 16) - 512;
+        const float ty0 = d1(ylo, phy, hy);
+        float gyz = __builtin_amdgcn_exp2f(-fmaf(ty0, ty0, tz2) * c);
+        float ry = __builtin_amdgcn_exp2f(-c * hy * fmaf(2.0f, ty0, hy));
         for (int my = ylo; my <= yhi; ++my) {
-            const float ty = d1(my, phy, B.dxf[1]);
+            const float ty = d1(my, phy, hy);
             const float ryz = fmaf(ty, ty, tz2);
-            if (ryz > cut) continue;
+            const float w = gyz;
+            gyz *= ry;
+            ry *= qy;
+            if (ryz > cutv) continue;
             int lo, hi;
-            row_range(phx, ryz, B, &B, slot, pid, my, mz, lo, hi);
+            row_range(phx, ryz, K, &B, slot, pid, my, mz, lo, hi);
             if (lo > hi) continue;
-            // y-z factor of the row: raw v_exp_f32 of -ryz c (in [-R^2 c, 0])
-            Z = fmaf(__builtin_amdgcn_exp2f(-ryz * B.cexp),
-                     sP[hi - mlo0 + 1][tid] - sP[lo - mlo0][tid], Z);
+            Z = fmaf(w, sP[hi - mlo0 + 1][tid] - sP[lo - mlo0][tid], Z);
         }
     }
     const float Zv = Z * (float)B.dV;
