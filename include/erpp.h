@@ -152,17 +152,40 @@ erpp_status erpp_plan_set_body_force(erpp_plan *plan, int32_t ibox, const double
  * D = m_p (u~ + (a_p^2/6) lap u~ - v)/tau_p with a_p the particle radius
  * (0, the default, turns it off).  lap u~ = the trilinear interpolation of the
  * 7-point nodal Laplacian of the carrier minus the Laplacian of the closed-form
- * self-disturbance (the projected Gaussian's second derivatives).  Added mass
- * and the Basset history force are not provided.  Synchronises the device and
- * invalidates captured graphs.  ERPP_EINVAL for a bad plan, index or radius. */
+ * self-disturbance (the projected Gaussian's second derivatives).  The added
+ * mass is set by erpp_plan_set_added_mass; the Basset history force is not
+ * provided.  Synchronises the device and invalidates captured graphs.
+ * ERPP_EINVAL for a bad plan, index or radius. */
 erpp_status erpp_plan_set_faxen(erpp_plan *plan, int32_t ibox, double a_p);
+
+/* Added-mass terms of box `ibox` (eq. force_particle, second line) for
+ * particles of radius a (0, the default, turns them off): displaced mass
+ * m_f = rho_f (4/3) pi a^3, and with u~ the carrier without the particle's own
+ * disturbance (its value, Laplacian and gradient at the particle each minus
+ * the closed form of the last injection's disturbance), the explicit Euler step
+ *   (m_p + m_f/2) (v^{n+1} - v^n)/dt = S + m_f Du~/Dt + (m_f/2) dq/dt + m_p g_b,
+ *   S = m_p (u~ + (a_p^2/6) lap u~ - v^n)/tau_p   (a_p: erpp_plan_set_faxen),
+ *   q = u~ + (a^2/10) lap u~,
+ *   dq/dt = (q^n - q^{n-1})/dt along the particle path, likewise du~/dt,
+ *   Du~/Dt = du~/dt + (u~ - v^n) . grad u~   (grad u~: trilinear interpolation
+ *            of the central-difference nodal gradient minus the closed form's),
+ * and the fluid receives the hydrodynamic force D = m_p (v^{n+1} - v^n)/dt -
+ * m_p g_b.  The path derivatives are zero on the first step after this call.
+ * hist: device, [6][np] FP64, caller-owned and left allocated while the terms
+ * are on: u~ and q of the last step, written by every update (its contents on
+ * entry are not read).  Explicit Euler only, boxes without mean shear only.
+ * Synchronises the device and invalidates captured graphs.  ERPP_EINVAL for a
+ * bad plan, index, radius or a NULL hist; ERPP_EUNSUPPORTED for another
+ * integrator or a sheared box. */
+erpp_status erpp_plan_set_added_mass(erpp_plan *plan, int32_t ibox, double a, double *hist);
 
 /* Particle integrator of every box (default ERPP_EULER).  The self-disturbance
  * removed from u~ is the same App. E closed form for both (the fluid receives
  * one forcing step of the handed-over drag either way; Heun removes it at
  * each stage's position).  Applies to later steps; invalidates captured graphs.
  * Synchronises the device.  ERPP_EINVAL for a bad plan or kind, or Heun with a
- * sheared box. */
+ * sheared box; ERPP_EUNSUPPORTED for another integrator than Euler while a box
+ * has the added-mass terms on. */
 erpp_status erpp_plan_set_integrator(erpp_plan *plan, erpp_integrator kind);
 
 /* Autotuner (ERPP_F32_FAST): times every candidate pencil shape on the plan's own

@@ -23,7 +23,8 @@ EXPORTS = ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile", "erpp
            "erpp_plan_bins", "erpp_bin", "erpp_scatter", "erpp_gather", "erpp_step", "erpp_run",
            "erpp_stage_times", "erpp_plan_destroy", "erpp_status_string", "erpp_last_error",
            "erpp_fluid_create", "erpp_fluid_step", "erpp_fluid_destroy", "erpp_run_coupled",
-           "erpp_plan_set_body_force", "erpp_plan_set_integrator", "erpp_plan_set_faxen"]
+           "erpp_plan_set_body_force", "erpp_plan_set_integrator", "erpp_plan_set_faxen",
+           "erpp_plan_set_added_mass"]
 
 
 class ErppError(RuntimeError):
@@ -81,11 +82,12 @@ def load(path: str = LIB_PATH):
     lib.erpp_plan_set_body_force.argtypes = [vp, i32, C.POINTER(d)]
     lib.erpp_plan_set_integrator.argtypes = [vp, C.c_int]
     lib.erpp_plan_set_faxen.argtypes = [vp, i32, d]
+    lib.erpp_plan_set_added_mass.argtypes = [vp, i32, d, vp]
     for name in ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile",
                  "erpp_plan_tune", "erpp_plan_bins", "erpp_bin", "erpp_scatter", "erpp_gather",
                  "erpp_step", "erpp_run", "erpp_stage_times", "erpp_fluid_create",
                  "erpp_fluid_step", "erpp_run_coupled", "erpp_plan_set_body_force",
-                 "erpp_plan_set_integrator", "erpp_plan_set_faxen"]:
+                 "erpp_plan_set_integrator", "erpp_plan_set_faxen", "erpp_plan_set_added_mass"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -210,6 +212,23 @@ class Plan:
     def set_faxen(self, ibox: int, a_p: float):
         """Particle radius of the Faxen term (a_p^2/6) lap u~ in the drag of box ibox."""
         _check(self.lib.erpp_plan_set_faxen(self.h, int(ibox), float(a_p)), "erpp_plan_set_faxen")
+
+    def set_added_mass(self, ibox: int, a: float, hist=None):
+        """Added-mass terms of box ibox for particles of radius a (0 turns them off).
+        hist: FP64 device tensor [6, np] (allocated here when None), kept by the
+        plan while the terms are on; it holds u~ and u~ + (a^2/10) lap u~ of the
+        last step."""
+        import torch
+        if a > 0.0 and hist is None:
+            np_ = self.boxes[ibox].x.shape[1]
+            hist = torch.zeros((6, np_), dtype=torch.float64, device=self.boxes[ibox].x.device)
+        if hist is not None and (hist.dtype != torch.float64 or not hist.is_contiguous()):
+            raise ValueError("hist must be a contiguous float64 tensor")
+        _check(self.lib.erpp_plan_set_added_mass(self.h, int(ibox), float(a), _ptr(hist)),
+               "erpp_plan_set_added_mass")
+        self._am_hist = getattr(self, "_am_hist", {})
+        self._am_hist[int(ibox)] = hist if a > 0.0 else None
+        return hist
 
     def set_integrator(self, kind: int):
         """EULER (explicit Euler), EXPONENTIAL (exact linear drag over the step) or

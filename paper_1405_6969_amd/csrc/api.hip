@@ -49,6 +49,12 @@ using erpp::hip_fail;
     } while (0)
 
 __global__ void k_set_step(int64_t *s, int64_t n) { *s = n; }
+
+// After an update with added mass: each such box now has a previous value.
+__global__ void k_am_mark(const erpp::DevBox *__restrict__ Bs, int nbox) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nbox && Bs[b].am_mf != 0.0) *Bs[b].am_valid = 1;
+}
 __global__ void k_advance_step(int64_t *s) { *s += 1; }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -80,6 +86,7 @@ void free_scratch(erpp_plan *p) {
     (void)hipFree(s.pphi);
     (void)hipFree(s.pbase);
     (void)hipFree(s.step);
+    (void)hipFree(s.am_valid);
     s = erpp::Scratch();
     (void)hipFree(p->dbox);
     p->dbox = nullptr;
@@ -163,6 +170,12 @@ namespace erpp {
 
 hipError_t set_step(erpp_plan *p, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, st, p->s.step, n);
+    return hipGetLastError();
+}
+
+hipError_t mark_added_mass(erpp_plan *p, hipStream_t st) {
+    hipLaunchKernelGGL(k_am_mark, dim3((unsigned)((p->nbox + 63) / 64)), dim3(64), 0, st, p->dbox,
+                       p->nbox);
     return hipGetLastError();
 }
 
@@ -370,7 +383,8 @@ erpp_status erpp_plan_create(erpp_plan **out, const erpp_box *boxes, int32_t nbo
         }
     }
     bool ok = alloc(&p->dbox, (size_t)nbox) == hipSuccess && alloc(&p->s.step, 2) == hipSuccess &&
-              alloc(&p->s.rank, (size_t)np_total) == hipSuccess;
+              alloc(&p->s.rank, (size_t)np_total) == hipSuccess &&
+              alloc(&p->s.am_valid, (size_t)nbox) == hipSuccess;
     if (ok && prec == ERPP_F32_FAST)
         ok = alloc(&p->s.rec, 2 * (size_t)np_total) == hipSuccess &&
              alloc(&p->s.bsum, (size_t)std::max<int64_t>(p->nkey_total, 1)) == hipSuccess &&
@@ -388,7 +402,10 @@ erpp_status erpp_plan_create(erpp_plan **out, const erpp_box *boxes, int32_t nbo
         (void)hipGetLastError();
         return fail(ERPP_ENOMEM, "plan scratch for %lld particles", (long long)np_total);
     }
+    for (int b = 0; b < nbox; ++b) p->hbox[b].am_valid = p->s.am_valid + b;
     erpp_status s = alloc_bins(p);
+    if (s == ERPP_OK && hipMemset(p->s.am_valid, 0, sizeof(int32_t) * nbox) != hipSuccess)
+        s = fail(ERPP_EHIP, "hipMemset of the added-mass flags");
     if (s == ERPP_OK) s = upload_boxes(p);
     if (s == ERPP_OK && hipMemset(p->s.step, 0, 2 * sizeof(int64_t)) != hipSuccess)
         s = fail(ERPP_EHIP, "hipMemset of the step counter");
@@ -446,10 +463,38 @@ erpp_status erpp_plan_set_faxen(erpp_plan *p, int32_t ibox, double a_p) {
     return ERPP_OK;
 }
 
+erpp_status erpp_plan_set_added_mass(erpp_plan *p, int32_t ibox, double a, double *hist) {
+    if (!p) return fail(ERPP_EINVAL, "plan is NULL");
+    if (ibox < 0 || ibox >= p->nbox) return fail(ERPP_EINVAL, "ibox %d out of range", ibox);
+    if (!std::isfinite(a) || a < 0.0) return fail(ERPP_EINVAL, "a must be finite and >= 0");
+    erpp::DevBox &B = p->hbox[ibox];
+    if (a > 0.0) {
+        if (!hist && B.np > 0) return fail(ERPP_EINVAL, "hist is NULL");
+        if (B.integ != 0)
+            return fail(ERPP_EUNSUPPORTED, "added mass runs with the explicit Euler integrator only");
+        if (B.shear != 0.0)
+            return fail(ERPP_EUNSUPPORTED, "box %d: added mass needs shear = 0 (the path "
+                                           "derivative would see the Lees-Edwards jump)", ibox);
+    }
+    B.am_mf = a > 0.0 ? B.rho_f * (4.0 / 3.0) * M_PI * a * a * a : 0.0;
+    B.am_fax = a * a / 10.0;
+    B.am_hist = a > 0.0 ? hist : nullptr;
+    drop_graph(p);     // the update kernel's instance depends on it
+    HIP_OR_RETURN(hipDeviceSynchronize());
+    HIP_OR_RETURN(hipMemset(B.am_valid, 0, sizeof(int32_t)));   // no previous value yet
+    HIP_OR_RETURN(hipMemcpy(p->dbox + ibox, &B, sizeof(erpp::DevBox), hipMemcpyHostToDevice));
+    return ERPP_OK;
+}
+
 erpp_status erpp_plan_set_integrator(erpp_plan *p, erpp_integrator kind) {
     if (!p) return fail(ERPP_EINVAL, "plan is NULL");
     if (kind != ERPP_EULER && kind != ERPP_EXPONENTIAL && kind != ERPP_HEUN)
         return fail(ERPP_EINVAL, "unknown integrator %d", (int)kind);
+    if (kind != ERPP_EULER)
+        for (int32_t b = 0; b < p->nbox; ++b)
+            if (p->hbox[b].am_mf != 0.0)
+                return fail(ERPP_EUNSUPPORTED, "box %d: the added-mass terms run with the "
+                                               "explicit Euler integrator only", b);
     if (kind == ERPP_HEUN)
         for (int32_t b = 0; b < p->nbox; ++b)
             if (p->boxes[b].shear != 0.0)

@@ -303,6 +303,150 @@ __device__ __forceinline__ void self_laplacian64(const double r[3], const double
     for (int c = 0; c < 3; ++c) out[c] = e * (D[c] * (rr * is * is - 2.0 * is) - r[c] * Dr * is * is);
 }
 
+// Gradient of the closed-form self-disturbance, out[3c + j] = d v_c / d x_j.
+// Writing the disturbance as v_c = pref [A D_c - (D.r) r_c H] with A = e - F and
+// H = (e - 3F) / r^2, functions of u = r^2 / (2s) (e = e^{-u}, s = sigma_s^2):
+// dF/du = (e - 3F) / (2u), so dA/d(r^2) = -(e/s + H)/2 and dH/d(r^2) = -K/2 with
+// K = (e/s + 5H) / r^2, and
+//   d_j v_c = pref [-(e/s + H) r_j D_c - H D_j r_c - H (D.r) delta_cj + K (D.r) r_c r_j].
+// Below eta = 0.3 (u < 0.09) H and K come from their power series in u, which
+// stay finite at r = 0 where the closed forms cancel.
+__device__ __forceinline__ void self_gradient64(const double r[3], const double D[3], double s,
+                                                double pref, double out[9]) {
+    const double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const double u = rr / (2.0 * s);
+    const double e = exp(-u);
+    const double Dr = D[0] * r[0] + D[1] * r[1] + D[2] * r[2];
+    double H, K;
+    if (u < 0.09) {
+        // H = (1/2s) sum_{m>=1} (-u)^(m-1) (-2m) / (m! (2m+3)), K likewise with 2m+5, over 2s^2
+        double c = -1.0;
+        H = 0.0;
+        K = 0.0;
+        for (int m = 1; m <= 8; ++m) {
+            H += (2.0 * m) * c / (2.0 * m + 3.0);
+            K += (2.0 * m) * c / (2.0 * m + 5.0);
+            c *= -u / (double)(m + 1);
+        }
+        H /= 2.0 * s;
+        K /= 2.0 * s * s;
+    } else {
+        const double eta = sqrt(u);
+        const double F = (0.88622692545275801365 * erf(eta) - eta * e) / (2.0 * eta * u);
+        H = (e - 3.0 * F) / rr;
+        K = (e / s + 5.0 * H) / rr;
+    }
+    const double a = e / s + H;
+    for (int c = 0; c < 3; ++c)
+        for (int j = 0; j < 3; ++j) {
+            double t = -a * r[j] * D[c] - H * D[j] * r[c] + K * Dr * r[c] * r[j];
+            if (c == j) t -= H * Dr;
+            out[3 * c + j] = pref * t;
+        }
+}
+
+// Trilinear interpolation at x of the central-difference nodal gradient of u,
+// out[3c + j] = d u_c / d x_j, plus the mean shear's d U_x / d y.
+template <typename T>
+__device__ void trilinear_gradient(const DevBox &B, const T *__restrict__ u, const double xp[3],
+                                   double out[9]) {
+    int b[3];
+    double ph[3];
+    for (int d = 0; d < 3; ++d) cell_of(xp[d], B.L[d], B.dx[d], B.n[d], b[d], ph[d]);
+    const int Nx = B.n[0], Ny = B.n[1], Nz = B.n[2];
+    const int64_t ng = (int64_t)Nx * Ny * Nz;
+    const double h[3] = {0.5 / B.dx[0], 0.5 / B.dx[1], 0.5 / B.dx[2]};
+    double acc[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int c2 = 0; c2 < 2; ++c2)
+        for (int c1 = 0; c1 < 2; ++c1)
+            for (int c0 = 0; c0 < 2; ++c0) {
+                const double w = (c0 ? ph[0] : 1.0 - ph[0]) * (c1 ? ph[1] : 1.0 - ph[1]) *
+                                 (c2 ? ph[2] : 1.0 - ph[2]);
+                const int i = wrap_node(b[0] + c0, Nx), j = wrap_node(b[1] + c1, Ny),
+                          k = wrap_node(b[2] + c2, Nz);
+                const int64_t xm = ((int64_t)k * Ny + j) * Nx + wrap_node(i - 1, Nx);
+                const int64_t xq = ((int64_t)k * Ny + j) * Nx + wrap_node(i + 1, Nx);
+                const int64_t ym = ((int64_t)k * Ny + wrap_node(j - 1, Ny)) * Nx + i;
+                const int64_t yq = ((int64_t)k * Ny + wrap_node(j + 1, Ny)) * Nx + i;
+                const int64_t zm = ((int64_t)wrap_node(k - 1, Nz) * Ny + j) * Nx + i;
+                const int64_t zq = ((int64_t)wrap_node(k + 1, Nz) * Ny + j) * Nx + i;
+                for (int c = 0; c < 3; ++c) {
+                    const T *uc = u + c * ng;
+                    acc[3 * c + 0] += w * (((double)uc[xq] - (double)uc[xm]) * h[0]);
+                    acc[3 * c + 1] += w * (((double)uc[yq] - (double)uc[ym]) * h[1]);
+                    acc[3 * c + 2] += w * (((double)uc[zq] - (double)uc[zm]) * h[2]);
+                }
+            }
+    acc[1] += B.shear;
+    for (int q = 0; q < 9; ++q) out[q] = acc[q];
+}
+
+// History write, position wrap (Lees-Edwards velocity jump in y when a mean
+// shear is present) and the new state.  FP64.
+__device__ __forceinline__ void finish_particle(const DevBox &B, int64_t p, const double xp[3],
+                                                const double D[3], const double xn[3],
+                                                double vn[3], double *hx, double *hdD,
+                                                float *hdF) {
+    const int64_t np = B.np;
+    for (int d = 0; d < 3; ++d) {
+        hx[d * np + p] = xp[d];
+        if (hdD) hdD[d * np + p] = D[d];
+        if (hdF) hdF[d * np + p] = (float)D[d];
+    }
+    for (int d = 0; d < 3; ++d) {
+        double L = B.L[d];
+        double fl = floor(xn[d] / L);
+        double w = xn[d] - L * fl;
+        int64_t k = (int64_t)fl;
+        if (w >= L) { w -= L; k += 1; }
+        if (w < 0.0) w = 0.0;
+        B.x[d * np + p] = w;
+        if (d == 1 && B.shear != 0.0 && k != 0) vn[0] -= (double)k * B.shear * L;
+    }
+    for (int d = 0; d < 3; ++d) B.v[d * np + p] = vn[d];
+}
+
+// Explicit Euler step with the added-mass terms (eq. force_particle, first two
+// lines), given u~ = u - v_self, lap u~ and grad u~ at x^n:
+//   (m_p + m_f/2) dv/dt = S + m_f Du~/Dt + (m_f/2) dq/dt + m_p g_b,
+//   S = m_p (u~ + fax lap u~ - v) / tau_p,   q = u~ + am_fax lap u~,
+//   Du~/Dt = du~/dt + (u~ - v) . grad u~,
+// with d/dt the difference along the particle path over the last step (zero on
+// the first step after the terms were switched on).  The fluid receives the
+// hydrodynamic force D = m_p dv/dt - m_p g_b.  FP64.
+__device__ __forceinline__ void update_particle_am(const DevBox &B, int64_t p, double dt,
+                                                   const double xp[3], const double ut[3],
+                                                   const double lap[3], const double grad[9],
+                                                   int valid, double *hx, double *hdD,
+                                                   float *hdF) {
+#pragma clang fp contract(off)
+    const int64_t np = B.np;
+    const double t = (double)B.tau[p];
+    const double mf = B.am_mf, mp = B.m_p;
+    double v[3], q[3], S[3], D[3], xn[3], vn[3];
+    for (int d = 0; d < 3; ++d) {
+        v[d] = B.v[d * np + p];
+        q[d] = ut[d] + B.am_fax * lap[d];
+        S[d] = mp * (ut[d] + B.fax * lap[d] - v[d]) / t;
+    }
+    for (int d = 0; d < 3; ++d) {
+        double conv = 0.0;
+        for (int j = 0; j < 3; ++j) conv += (ut[j] - v[j]) * grad[3 * d + j];
+        const double dut = valid ? (ut[d] - B.am_hist[d * np + p]) / dt : 0.0;
+        const double dq = valid ? (q[d] - B.am_hist[(3 + d) * np + p]) / dt : 0.0;
+        const double Dm = dut + conv;
+        const double acc = (S[d] + mf * Dm + 0.5 * mf * dq + mp * B.gb[d]) / (mp + 0.5 * mf);
+        D[d] = S[d] + mf * Dm + 0.5 * mf * (dq - acc);
+        xn[d] = xp[d] + dt * v[d];
+        vn[d] = v[d] + dt * acc;
+    }
+    for (int d = 0; d < 3; ++d) {
+        B.am_hist[d * np + p] = ut[d];
+        B.am_hist[(3 + d) * np + p] = q[d];
+    }
+    finish_particle(B, p, xp, D, xn, vn, hx, hdD, hdF);
+}
+
 // Drag, history write, explicit Euler and periodic wrap (Lees-Edwards velocity
 // jump in y when a mean shear is present).  FP64.
 __device__ __forceinline__ void update_particle(const DevBox &B, int64_t p, double dt,
@@ -357,22 +501,7 @@ __device__ __forceinline__ void update_particle(const DevBox &B, int64_t p, doub
             D[d] = B.m_p * (vn[d] - vd) / dt - B.m_p * B.gb[d];
         }
     }
-    for (int d = 0; d < 3; ++d) {
-        hx[d * np + p] = xp[d];
-        if (hdD) hdD[d * np + p] = D[d];
-        if (hdF) hdF[d * np + p] = (float)D[d];
-    }
-    for (int d = 0; d < 3; ++d) {
-        double L = B.L[d];
-        double fl = floor(xn[d] / L);
-        double w = xn[d] - L * fl;
-        int64_t k = (int64_t)fl;
-        if (w >= L) { w -= L; k += 1; }
-        if (w < 0.0) w = 0.0;
-        B.x[d * np + p] = w;
-        if (d == 1 && B.shear != 0.0 && k != 0) vn[0] -= (double)k * B.shear * L;
-    }
-    for (int d = 0; d < 3; ++d) B.v[d * np + p] = vn[d];
+    finish_particle(B, p, xp, D, xn, vn, hx, hdD, hdF);
 }
 
 }  // namespace erpp

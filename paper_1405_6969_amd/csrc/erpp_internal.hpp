@@ -33,7 +33,7 @@ struct DevBox {
     int64_t cell_off;    // first cell of this box in the concatenated cell space (erpp_bin)
     int64_t key_off;     // first key of this box in the step's (row, x-block) key space
     int32_t nxb;         // x-blocks per cell row
-    int32_t integ;       // particle integrator: 0 explicit Euler, 1 exponential
+    int32_t integ;       // particle integrator: 0 explicit Euler, 1 exponential, 2 Heun
     int64_t blk_p;       // first block of this box in particle launches
     int64_t blk_t;       // first block of this box in tile launches
     int64_t blk_b;       // first block of this box in (cell row, x-block) launches
@@ -47,6 +47,10 @@ struct DevBox {
     double m_p, rho_f, shear;
     double gb[3];        // body acceleration of the particles, (m_p - m_f) g / m_p
     double fax;          // Faxen coefficient a_p^2 / 6 (0: no Faxen term)
+    double am_mf;        // added mass: displaced fluid mass m_f (0: no added-mass terms)
+    double am_fax;       // added mass: Faxen coefficient a^2 / 10 of its d/dt term
+    double *am_hist;     // added mass: [6][np] u~ and u~ + am_fax lap u~ of the last step
+    int32_t *am_valid;   // added mass: 0 until the first step with the terms has run
     double s2s;          // sigma_s^2 = sigma^2 + 2 nu dt  (self-disturbance width)
     double pref;         // -(dt/rho_f) (2 pi sigma_s^2)^(-3/2)
     float dxf[3];
@@ -81,6 +85,7 @@ struct Scratch {
     double *pphi = nullptr;      // [3][np_total] offsets inside the base cell
     int32_t *pbase = nullptr;    // [3][np_total] base cell
     // both
+    int32_t *am_valid = nullptr; // [nbox]          added-mass history present (per box)
     int64_t *step = nullptr;     // [2] step index: [0] next step to run (set by the host,
                                  // advanced by the scan of the fast path or by a kernel
                                  // of its own in the plain path), [1] the step in progress
@@ -144,6 +149,7 @@ hipError_t plain_scatter_stages(erpp_plan *p, hipStream_t st);
 hipError_t plain_update_stage(erpp_plan *p, hipStream_t st);
 hipError_t set_step(erpp_plan *p, int64_t n, hipStream_t st);
 hipError_t advance_step(erpp_plan *p, hipStream_t st);
+hipError_t mark_added_mass(erpp_plan *p, hipStream_t st);  // after an update: history present
 bool fill_box_tiles(erpp_plan *p);          // tiles, blocks, LDS layout; false if it does not fit
 // start = exclusive scan of count, count = 0; with stepp, also step[1] = step[0]++
 hipError_t scan_counts(int32_t *count, int64_t n, int32_t *start, int32_t *part, int32_t *ticket,

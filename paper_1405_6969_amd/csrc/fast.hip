@@ -817,7 +817,35 @@ __device__ __forceinline__ void self_terms(const DevBox &B, int64_t p, int64_t n
 // FAX: some box of the plan has a Faxen term; HEUN: some box uses the Heun
 // integrator (second stage at x* = x^n + dt v^n).  Their extra work doubles the
 // registers, so plans without them run the lean instance.
-template <bool FAX, bool HEUN>
+// Laplacian and gradient of u~ = u - v_self at pos for the added-mass terms:
+// interpolated nodal stencils of the carrier minus the closed forms of the
+// self-disturbance of the last injection (FP64).
+__device__ __forceinline__ void am_terms(const DevBox &B, int64_t p, int64_t n, int M, int selfc,
+                                         const double pos[3], double lap[3], double grad[9]) {
+    trilinear_laplacian<float>(B, (const float *)B.u, pos, lap);
+    trilinear_gradient<float>(B, (const float *)B.u, pos, grad);
+    if (selfc && n >= M + 1) {
+        const int64_t np = B.np;
+        const int64_t ss = (n - 1 - M) % (M + 1);
+        const double *Xs = B.ring_x + ss * 3 * np;
+        const float *Ds = (const float *)B.ring_d + ss * 3 * np;
+        double r[3], D[3], ls[3], gs[9];
+        for (int d = 0; d < 3; ++d) {
+            double rd = pos[d] - Xs[d * np + p];
+            rd -= B.L[d] * rint(rd / B.L[d]);
+            r[d] = rd;
+            D[d] = (double)Ds[d * np + p];
+        }
+        self_laplacian64(r, D, B.s2s, B.pref, ls);
+        self_gradient64(r, D, B.s2s, B.pref, gs);
+        for (int d = 0; d < 3; ++d) lap[d] -= ls[d];
+        for (int q = 0; q < 9; ++q) grad[q] -= gs[q];
+    }
+}
+
+// AM: the added-mass terms are on for some box (explicit Euler only); boxes
+// without them take the plain Euler step.
+template <bool FAX, bool HEUN, bool AM>
 __global__ void __launch_bounds__(kBlock) k_update(const DevBox *__restrict__ Bs, int nbox,
                                                    const int64_t *__restrict__ stepp, int M,
                                                    double dt, int selfc,
@@ -840,6 +868,16 @@ __global__ void __launch_bounds__(kBlock) k_update(const DevBox *__restrict__ Bs
     } else {
         trilinear<float>(B, (const float *)B.u, xp, up);
     }
+    const int64_t sw = n % (M + 1);
+    if (AM && B.am_mf != 0.0) {
+        double vs[3], ut[3], lap[3], grad[9];
+        self_terms<false>(B, p, n, M, selfc, xp, up, vs);
+        for (int d = 0; d < 3; ++d) ut[d] = up[d] - vs[d];
+        am_terms(B, p, n, M, selfc, xp, lap, grad);
+        update_particle_am(B, p, dt, xp, ut, lap, grad, *B.am_valid, B.ring_x + sw * 3 * np,
+                           nullptr, (float *)B.ring_d + sw * 3 * np);
+        return;
+    }
     double vs[3];
     self_terms<FAX>(B, p, n, M, selfc, xp, up, vs);
     double up2[3] = {0.0, 0.0, 0.0}, vs2[3] = {0.0, 0.0, 0.0};
@@ -849,7 +887,6 @@ __global__ void __launch_bounds__(kBlock) k_update(const DevBox *__restrict__ Bs
         trilinear<float>(B, (const float *)B.u, xs, up2);
         self_terms<FAX>(B, p, n, M, selfc, xs, up2, vs2);
     }
-    const int64_t sw = n % (M + 1);
     update_particle(B, p, dt, xp, up, vs, up2, vs2, B.ring_x + sw * 3 * np, nullptr,
                     (float *)B.ring_d + sw * 3 * np);
 }
@@ -977,17 +1014,22 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                 hipLaunchKernelGGL(k_gather_sorted, dim3((unsigned)grid), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->pblocks, P->s.step + 1, P->M, P->s.xs,
                                    P->s.up);
-                bool fax = false, heun = false;
+                bool fax = false, heun = false, am = false;
                 for (const auto &B : P->hbox) {
                     fax = fax || B.fax != 0.0;
                     heun = heun || B.integ == 2;
+                    am = am || B.am_mf != 0.0;
                 }
-                auto upd = fax ? (heun ? k_update<true, true> : k_update<true, false>)
-                               : (heun ? k_update<false, true> : k_update<false, false>);
+                // added mass runs with explicit Euler only (checked by the setters)
+                auto upd = am ? (fax ? k_update<true, false, true> : k_update<false, false, true>)
+                         : fax ? (heun ? k_update<true, true, false> : k_update<true, false, false>)
+                               : (heun ? k_update<false, true, false>
+                                       : k_update<false, false, false>);
                 hipLaunchKernelGGL(upd,
                                    dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step + 1, P->M, P->dt, P->self_correction,
                                    P->s.up, P->s.sl);
+                if (am) return mark_added_mass(P, st);
             }
             break;
         default:

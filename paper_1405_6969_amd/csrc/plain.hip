@@ -145,6 +145,39 @@ __device__ __forceinline__ void plain_terms(const DevBox &B, int64_t p, int64_t 
     }
 }
 
+// Added mass: u~ = u - v_self, lap u~ and grad u~ at pos, each the
+// interpolated carrier stencil minus the closed form of the self-disturbance of
+// the last injection (FP64).
+__device__ void plain_am_terms(const DevBox &B, int64_t p, int64_t n, int M, int selfc,
+                               const double pos[3], double ut[3], double lap[3],
+                               double grad[9]) {
+    const int64_t np = B.np;
+    const double *u = (const double *)B.u;
+    trilinear<double>(B, u, pos, ut);
+    trilinear_laplacian<double>(B, u, pos, lap);
+    trilinear_gradient<double>(B, u, pos, grad);
+    if (selfc && n >= M + 1) {
+        const int64_t ss = (n - 1 - M) % (M + 1);
+        const double *Xs = B.ring_x + ss * 3 * np;
+        const double *Ds = (const double *)B.ring_d + ss * 3 * np;
+        double r[3], D[3], vs[3], ls[3], gs[9];
+        for (int d = 0; d < 3; ++d) {
+            double rd = pos[d] - Xs[d * np + p];
+            rd -= B.L[d] * rint(rd / B.L[d]);
+            r[d] = rd;
+            D[d] = Ds[d * np + p];
+        }
+        self_disturbance64(r, D, B.s2s, B.pref, vs);
+        self_laplacian64(r, D, B.s2s, B.pref, ls);
+        self_gradient64(r, D, B.s2s, B.pref, gs);
+        for (int d = 0; d < 3; ++d) {
+            ut[d] -= vs[d];
+            lap[d] -= ls[d];
+        }
+        for (int q = 0; q < 9; ++q) grad[q] -= gs[q];
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_plain_update(const DevBox *__restrict__ Bs, int nbox,
                                                          const int64_t *__restrict__ stepp, int M,
                                                          double dt, int selfc) {
@@ -155,6 +188,14 @@ __global__ void __launch_bounds__(kBlock) k_plain_update(const DevBox *__restric
     const int64_t n = *stepp;
     const int64_t np = B.np;
     double xp[3] = {B.x[p], B.x[np + p], B.x[2 * np + p]};
+    const int64_t sw = n % (M + 1);
+    if (B.am_mf != 0.0) {
+        double ut[3], lap[3], grad[9];
+        plain_am_terms(B, p, n, M, selfc, xp, ut, lap, grad);
+        update_particle_am(B, p, dt, xp, ut, lap, grad, *B.am_valid, B.ring_x + sw * 3 * np,
+                           (double *)B.ring_d + sw * 3 * np, nullptr);
+        return;
+    }
     double up[3], vs[3];
     plain_terms(B, p, n, M, selfc, xp, up, vs);
     double up2[3] = {0.0, 0.0, 0.0}, vs2[3] = {0.0, 0.0, 0.0};
@@ -164,7 +205,6 @@ __global__ void __launch_bounds__(kBlock) k_plain_update(const DevBox *__restric
                               xp[2] + dt * B.v[2 * np + p]};
         plain_terms(B, p, n, M, selfc, xs, up2, vs2);
     }
-    const int64_t sw = n % (M + 1);
     update_particle(B, p, dt, xp, up, vs, up2, vs2, B.ring_x + sw * 3 * np,
                     (double *)B.ring_d + sw * 3 * np, nullptr);
 }
@@ -198,9 +238,12 @@ hipError_t plain_stage(erpp_plan *P, int k, hipStream_t st) {
                                    P->s.pphi, P->s.pbase, P->np_total);
             break;
         case 4:
-            if (P->np_total > 0)
+            if (P->np_total > 0) {
                 hipLaunchKernelGGL(k_plain_update, dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step, P->M, P->dt, P->self_correction);
+                for (const auto &B : P->hbox)
+                    if (B.am_mf != 0.0) return mark_added_mass(P, st);
+            }
             break;
         default:
             return hipErrorInvalidValue;
