@@ -144,3 +144,14 @@ def test_fluid_step_null_arguments():
     erpp, lib = _lib()
     assert lib.erpp_fluid_step(None, None, None, None) == -1
     lib.erpp_fluid_destroy(None)
+
+
+def test_setters_reject_a_null_plan():
+    """Every per-plan setter validates its plan before touching the device."""
+    erpp, lib = _lib()
+    g = (C.c_double * 3)(0.0, 0.0, 0.0)
+    assert lib.erpp_plan_set_body_force(None, 0, g) == erpp.ERPP_EINVAL
+    assert lib.erpp_plan_set_faxen(None, 0, C.c_double(0.1)) == erpp.ERPP_EINVAL
+    assert lib.erpp_plan_set_integrator(None, 0) == erpp.ERPP_EINVAL
+    assert lib.erpp_plan_set_added_mass(None, 0, C.c_double(0.1), None) == erpp.ERPP_EINVAL
+    assert lib.erpp_last_error()
