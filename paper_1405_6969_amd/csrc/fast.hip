@@ -348,9 +348,13 @@ __global__ void __launch_bounds__(kBlock) k_block_sums(const DevBox *__restrict_
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
+#pragma unroll 4
         for (int g = g0[k]; g < g1[k]; ++g) s += (double)rec_amax(rec, g);
     bsum[B.key_off + e] = __double2float_ru(s);
 }
+
+static_assert(kBlock % kBoundXChunk == 0 && (kBoundXChunk & (kBoundXChunk - 1)) == 0,
+              "the window load maps a power-of-two chunk of x-blocks onto the block");
 
 __global__ void __launch_bounds__(kBlock) k_pencil_scale(const DevBox *__restrict__ Bs, int nbox,
                                                          const int64_t *__restrict__ stepp, int M,
@@ -407,22 +411,45 @@ __global__ void __launch_bounds__(kBlock) k_pencil_scale(const DevBox *__restric
     float bmax = 0.0f;
     for (int X0 = 0; X0 < nxb; X0 += kBoundXChunk) {
         const int nx = min(kBoundXChunk, nxb - X0);
-        // window cell rows b1 = o1 - mhi1 + wy, b2 = o2 - mhi2 + wz (periodic)
-        for (int k = tid; k < WZ * WY * nx; k += kBlock) {
-            const int X = k % nx, r = k / nx;
-            const int wy = r % WY, wz = r / WY;
-            int b1 = o1 - mhi1 + wy, b2 = o2 - mhi2 + wz;
-            b1 += (b1 < 0) ? Ny : 0;
-            b1 -= (b1 >= Ny) ? Ny : 0;
-            b2 += (b2 < 0) ? Nz : 0;
-            b2 -= (b2 >= Nz) ? Nz : 0;
-            win[r * kBoundXChunk + X] = bsum[B.key_off + ((int64_t)b2 * Ny + b1) * nxb + X0 + X];
-        }
-        if (nx < kBoundXChunk)
-            for (int k = tid; k < WZ * WY * (kBoundXChunk - nx); k += kBlock) {
-                const int X = nx + k % (kBoundXChunk - nx), r = k / (kBoundXChunk - nx);
-                win[r * kBoundXChunk + X] = 0.0f;
+        // window cell rows b1 = o1 - mhi1 + wy, b2 = o2 - mhi2 + wz (periodic): thread
+        // t fills column X = t mod 16 of rows t/16, t/16 + 16, ... (entries past nx
+        // are zero), its (wy, wz) advanced without a division per entry
+        {
+            constexpr int kRowStep = kBlock / kBoundXChunk;
+            constexpr int kBatch = 8;
+            const int X = tid & (kBoundXChunk - 1);
+            const int Xc = min(X, nx - 1);
+            const int total = WZ * WY;
+            int r0 = tid / kBoundXChunk;
+            int wz = r0 / WY, wy = r0 - wz * WY;
+            const int sz = kRowStep / WY, sy = kRowStep - sz * WY;
+            for (; r0 < total; r0 += kBatch * kRowStep) {
+                // kBatch loads in flight: every address is valid (rows past the
+                // window re-read its last plane, padding columns column nx - 1) and
+                // the values are masked when stored
+                float v[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    int b1 = o1 - mhi1 + wy, b2 = o2 - mhi2 + min(wz, WZ - 1);
+                    b1 += (b1 < 0) ? Ny : 0;
+                    b1 -= (b1 >= Ny) ? Ny : 0;
+                    b2 += (b2 < 0) ? Nz : 0;
+                    b2 -= (b2 >= Nz) ? Nz : 0;
+                    v[u] = bsum[B.key_off + ((int64_t)b2 * Ny + b1) * nxb + X0 + Xc];
+                    wy += sy;
+                    wz += sz;
+                    if (wy >= WY) {
+                        wy -= WY;
+                        ++wz;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const int r = r0 + u * kRowStep;
+                    if (r < total) win[r * kBoundXChunk + X] = (X < nx) ? v[u] : 0.0f;
+                }
             }
+        }
         __syncthreads();
         // four x-blocks per thread (128-bit LDS reads; entries past nx are zero)
         const int nq = (nx + 3) / 4;
