@@ -42,6 +42,7 @@ def _fill_level(db, slot, X, D):
     ((64, 24, 20), 3000, 1.5, (0, 1, 1), "uniform"),
     ((64, 40, 24), 3000, 1.5, (1024, 32, 1), "clustered"),  # 1024-thread workgroups
     ((20, 18, 16), 300, 0.3, (0, 4, 4), "uniform"),          # unresolved: 3 sigma < dx
+    ((40, 36, 32), 1500, 2.4, (0, 8, 2), "clustered"),       # widest stencil: 16 nodes a side
 ])
 def test_scatter_matches_oracle(prec, shape, np_, sigma_dx, tile, placement):
     _cuda()
@@ -311,3 +312,21 @@ def test_tuner_picks_a_valid_tile(tmp_path):
     with erpp.Plan([db2], w.M, w.dt) as plan2:
         plan2.tune(cache)                       # cache hit, no timing
         assert plan2.get_tile() == t
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_step_with_no_particles(prec):
+    """A plan whose only box holds no particle: every stage launches nothing or
+    exits at once, the forcing is zero, and a graph replay works."""
+    _cuda()
+    spec = workloads.BoxSpec(n=(16, 16, 16), L=(1.0, 1.0, 1.0), np_=0, seed=3)
+    box = workloads.make_box(spec)
+    M = 2
+    db = upload(box, M, prec)
+    db.f.fill_(7.0)
+    with erpp.Plan([db], M, 1e-3, precision=prec) as plan:
+        for n in range(M + 2):
+            plan.step(n)
+        plan.run(M + 2, 3, graph=True)
+        torch.cuda.synchronize()
+        assert not torch.any(db.f != 0).item()
