@@ -539,6 +539,7 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
     extern __shared__ int32_t lds[];
     __shared__ int s_cls[256];
     __shared__ int s_ncls;
+    __shared__ int s_next;                // next class to hand out
     const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_t; });
     const DevBox &B = Bs[bi];
     const int t = (int)(blockIdx.x - B.blk_t);
@@ -551,7 +552,7 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
     const int PXa = B.pxa;                 // words per unwrapped row (per component)
     int32_t *acc = lds;                    // [T2][T1][PXa][3]
     int *tab = lds + B.lds_tab;            // record-start table of the window
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
     const int mlo0 = B.mlo[0], mhi0 = B.mhi[0];
     const int mlo1 = B.mlo[1], mhi1 = B.mhi[1];
     const int mlo2 = B.mlo[2], mhi2 = B.mhi[2];
@@ -575,7 +576,10 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
         // a base-cell offset in [0, 1)^2 within the cut-off
         const float cut = B.R2f + B.guard;
         const int ny = mhi1 - mlo1 + 1, nz = mhi2 - mlo2 + 1;
-        if (tid == 0) s_ncls = 0;
+        if (tid == 0) {
+            s_ncls = 0;
+            s_next = 0;
+        }
         __syncthreads();
         if (tid < ny * nz) {
             const int dy = mlo1 + tid % ny, dz = mlo2 + tid / ny;
@@ -615,7 +619,13 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
                      "+v"(cutv));
         const int ncls = s_ncls;
         const int nr = 2 * e2;
-        for (int ci = wv; ci < ncls; ci += NT / 64) {
+        // classes are handed out to the waves as they finish the previous one (the
+        // classes differ in size, so a fixed round-robin leaves waves idle at the end)
+        for (;;) {
+            int cn = 0;
+            if (lane == 0) cn = atomicAdd(&s_next, 1);
+            const int ci = __builtin_amdgcn_readfirstlane(cn);
+            if (ci >= ncls) break;
             const int cl = s_cls[ci];
             const int dy = mlo1 + cl % ny, dz = mlo2 + cl / ny;
             // lane k < 2 e2: part (k & 1) of the records of plane k >> 1.  Part 0
