@@ -221,6 +221,15 @@ def test_step_config2_reduced(prec):
     _run_parity(workloads.make_boxes(w), w.M, w.dt, w.M + 6, prec, every=3)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_step_shortest_delay(prec):
+    """M = 1: a ring of two levels, where the update reads the self term from the
+    slot it then overwrites and the scatter reads the other one."""
+    _cuda()
+    w = workloads.config(1, np_=800)
+    _run_parity(workloads.make_boxes(w), 1, w.dt, 8, prec)
+
+
 def test_step_self_correction_off():
     _cuda()
     w = workloads.config(1, np_=500)
