@@ -535,14 +535,19 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
                                                            int M,
                                                            const int32_t *__restrict__ start,
                                                            const float4 *__restrict__ rec,
-                                                           const float *__restrict__ pscale) {
+                                                           const float *__restrict__ pscale,
+                                                           int64_t npen) {
     extern __shared__ int32_t lds[];
     __shared__ int s_cls[256];
     __shared__ int s_ncls;
     __shared__ int s_next;                // next class to hand out
-    const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_t; });
+    // workgroups are dealt to the 8 XCDs round-robin; give each XCD (its own L2)
+    // one contiguous run of pencils, whose record windows overlap
+    const int64_t pen = xcd_block(blockIdx.x, gridDim.x);
+    if (pen >= npen) return;
+    const int bi = box_of_block(Bs, nbox, pen, [](const DevBox &b) { return b.blk_t; });
     const DevBox &B = Bs[bi];
-    const int t = (int)(blockIdx.x - B.blk_t);
+    const int t = (int)(pen - B.blk_t);
     const int T1 = B.T[1], T2 = B.T[2];
     const int o1 = (t % B.ntile[1]) * T1;
     const int o2 = (t / B.ntile[1]) * T2;
@@ -604,7 +609,7 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
             }
         };
         // fixed-point scale of the pencil (k_pencil_scale)
-        scale = pscale[blockIdx.x];
+        scale = pscale[pen];
         const int64_t slot = (n - M) % (M + 1);
         float hx = B.dxf[0], hy = B.dxf[1], hz = B.dxf[2];
         float c = B.cexp;
@@ -1040,9 +1045,10 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                 hipLaunchKernelGGL(k_pencil_scale, dim3((unsigned)P->tblocks), dim3(kBlock),
                                    P->bound_lds, st, P->dbox, P->nbox, P->s.step + 1, P->M,
                                    P->s.bsum, P->s.pscale);
-                hipLaunchKernelGGL(fn, dim3((unsigned)P->tblocks), dim3(big ? 1024 : 512),
+                const int64_t pgrid = (P->tblocks + kXcds - 1) / kXcds * kXcds;
+                hipLaunchKernelGGL(fn, dim3((unsigned)pgrid), dim3(big ? 1024 : 512),
                                    P->lds_bytes, st, P->dbox, P->nbox, P->s.step + 1, P->M,
-                                   P->s.start, P->s.rec, P->s.pscale);
+                                   P->s.start, P->s.rec, P->s.pscale, P->tblocks);
             }
             break;
         case 4:
