@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-steps", type=int, default=10)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the particle-force variants (integrators, Faxen, added mass)")
     ap.add_argument("--no-coupled", action="store_true",
                     help="skip the two-way coupled run (coupling step + fluid step)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -248,6 +250,11 @@ def main():
         torch.cuda.empty_cache()
         coupled = bench_coupled(boxes[0], w, tile, min(K, 100), erpp, torch)
         log(f"[bench] coupled {coupled}")
+    variants = None
+    if not args.no_variants and len(boxes) == 1:
+        torch.cuda.empty_cache()
+        variants = bench_variants(boxes[0], w, tile, min(K, 100), erpp, torch)
+        log(f"[bench] variants {variants}")
     if args.copy_calibration > 0:
         nel = args.copy_calibration * (1 << 20) // 4
         src = torch.ones(nel, dtype=torch.float32, device="cuda")
@@ -274,6 +281,7 @@ def main():
         "accuracy": accuracy,
         "cpu_baseline": cpu,
         "coupled": coupled,
+        "variants": variants,
     }
     print(json.dumps(out), flush=True)
 
@@ -323,6 +331,51 @@ def bench_coupled(box, w, tile, K, erpp, torch):
             "fluid_step": {"us": round(fms * 1e3, 1), "grid": list(box.n),
                            "algorithmic_bytes": fbytes,
                            "achieved_gbs": round(fbytes / (fms * 1e-3) / 1e9, 1)}}
+
+
+def bench_variants(box, w, tile, K, erpp, torch):
+    """The particle-force options on the same particles and carrier without the
+    mean shear (Heun and the added mass are defined for boxes at rest): the
+    coupling step per graph replay and the update stage alone (HIP events), for
+    explicit Euler, the exponential integrator, Heun with the self term removed
+    at each stage, the Faxen term (a_p = 0.6 dx) and the added mass on top of it
+    (a = 0.6 dx).  Units: ms per step, us for the update stage."""
+    M, dt, s = w.M, w.dt, box.spec
+    v = box.v.copy()
+    if s.shear != 0.0:
+        v[0] -= s.shear * (box.x[1] - 0.5 * box.L[1])
+    a_p = 0.6 * box.dx[0]
+    cases = [("euler", None, 0.0, 0.0), ("exponential", erpp.EXPONENTIAL, 0.0, 0.0),
+             ("heun", erpp.HEUN, 0.0, 0.0), ("faxen", None, a_p, 0.0),
+             ("added_mass", None, a_p, a_p)]
+    out = {"workload": f"{w.name} without mean shear", "steps": K, "a_p": round(a_p, 6)}
+    for name, integ, fax, am in cases:
+        db = erpp.device_box(box.n, box.L, box.x, v, box.tau, box.u.astype(np.float32), M,
+                             box.m_p, s.rho_f, s.nu, box.sigma, s.cutoff, 0.0,
+                             precision=erpp.F32_FAST)
+        plan = erpp.Plan([db], M, dt, precision=erpp.F32_FAST)
+        plan.set_tile(tile)
+        if integ is not None:
+            plan.set_integrator(integ)
+        if fax > 0.0:
+            plan.set_faxen(0, fax)
+        if am > 0.0:
+            plan.set_added_mass(0, am)
+        warm = M + 4
+        plan.run(0, warm, graph=True)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        plan.run(warm, K, graph=True)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / K
+        st = plan.stage_times(warm + K, 10)
+        out[name] = {"ms_per_step": round(ms, 4), "update_us": round(st[4] * 1e3, 1)}
+        plan.close()
+        del db
+    torch.cuda.empty_cache()
+    return out
 
 
 def check_accuracy(box, db, w, steps_done):

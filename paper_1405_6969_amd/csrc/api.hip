@@ -87,6 +87,8 @@ void free_scratch(erpp_plan *p) {
     (void)hipFree(s.pbase);
     (void)hipFree(s.step);
     (void)hipFree(s.am_valid);
+    (void)hipFree(s.aux);
+    (void)hipFree(s.vrec);
     s = erpp::Scratch();
     (void)hipFree(p->dbox);
     p->dbox = nullptr;
@@ -185,6 +187,23 @@ hipError_t advance_step(erpp_plan *p, hipStream_t st) {
 }
 
 static int32_t round4(int64_t v) { return (int32_t)((v + 3) & ~int64_t(3)); }
+
+// Record-order buffers of the optional forces' grid terms, allocated on first use
+// (outside any step, by the setters).
+erpp_status ensure_aux(erpp_plan *p) {
+    if (p->prec != ERPP_F32_FAST || p->s.aux) return ERPP_OK;
+    HIP_OR_RETURN(hipDeviceSynchronize());
+    if (alloc(&p->s.aux, (size_t)kAux * (size_t)std::max<int64_t>(p->np_total, 1)) != hipSuccess ||
+        alloc(&p->s.vrec, (size_t)std::max<int64_t>(p->np_total, 1)) != hipSuccess) {
+        (void)hipFree(p->s.aux);
+        (void)hipFree(p->s.vrec);
+        p->s.aux = nullptr;
+        p->s.vrec = nullptr;
+        (void)hipGetLastError();
+        return fail(ERPP_ENOMEM, "record-order buffers of the particle forces");
+    }
+    return ERPP_OK;
+}
 
 // Pencils, block offsets and the scatter's LDS layout of every box for the
 // plan's tile.  Returns false when a pencil does not fit the LDS.
@@ -455,6 +474,10 @@ erpp_status erpp_plan_set_faxen(erpp_plan *p, int32_t ibox, double a_p) {
     if (!p) return fail(ERPP_EINVAL, "plan is NULL");
     if (ibox < 0 || ibox >= p->nbox) return fail(ERPP_EINVAL, "ibox %d out of range", ibox);
     if (!std::isfinite(a_p) || a_p < 0.0) return fail(ERPP_EINVAL, "a_p must be finite and >= 0");
+    if (a_p > 0.0) {
+        erpp_status s = erpp::ensure_aux(p);
+        if (s != ERPP_OK) return s;
+    }
     p->hbox[ibox].fax = a_p * a_p / 6.0;
     drop_graph(p);     // the update kernel's instance depends on it
     HIP_OR_RETURN(hipDeviceSynchronize());
@@ -462,6 +485,7 @@ erpp_status erpp_plan_set_faxen(erpp_plan *p, int32_t ibox, double a_p) {
                             hipMemcpyHostToDevice));
     return ERPP_OK;
 }
+
 
 erpp_status erpp_plan_set_added_mass(erpp_plan *p, int32_t ibox, double a, double *hist) {
     if (!p) return fail(ERPP_EINVAL, "plan is NULL");
@@ -475,6 +499,10 @@ erpp_status erpp_plan_set_added_mass(erpp_plan *p, int32_t ibox, double a, doubl
         if (B.shear != 0.0)
             return fail(ERPP_EUNSUPPORTED, "box %d: added mass needs shear = 0 (the path "
                                            "derivative would see the Lees-Edwards jump)", ibox);
+    }
+    if (a > 0.0) {
+        erpp_status s = erpp::ensure_aux(p);
+        if (s != ERPP_OK) return s;
     }
     B.am_mf = a > 0.0 ? B.rho_f * (4.0 / 3.0) * M_PI * a * a * a : 0.0;
     B.am_fax = a * a / 10.0;
@@ -500,6 +528,10 @@ erpp_status erpp_plan_set_integrator(erpp_plan *p, erpp_integrator kind) {
             if (p->boxes[b].shear != 0.0)
                 return fail(ERPP_EINVAL, "box %d: Heun needs shear = 0 (its second stage would "
                                          "straddle the Lees-Edwards jump)", b);
+    if (kind == ERPP_HEUN) {
+        erpp_status s = erpp::ensure_aux(p);
+        if (s != ERPP_OK) return s;
+    }
     for (auto &B : p->hbox) B.integ = (int32_t)kind;
     drop_graph(p);     // the update kernel's instance depends on it
     HIP_OR_RETURN(hipDeviceSynchronize());

@@ -16,6 +16,7 @@ constexpr int kMaxTileZ = 8;
 constexpr int kBlock = 256;          // threads per block of particle kernels
 constexpr int kScanChunk = 4096;     // counters per block of the device-wide scan
 constexpr int kXBlockShift = 4;      // step binning: x-blocks of 16 cells per cell row
+constexpr int kAux = 6;              // record-order grid terms: lap, grad x3, u(x*), lap(x*)
 constexpr int kBoundXChunk = 16;     // x-blocks per LDS pass of the pencil-scale kernel
 
 // Everything a kernel needs to know about one box; lives in device memory as
@@ -80,6 +81,11 @@ struct Scratch {
     double4 *xs = nullptr;       // [np_total]      x^n in record order
     double4 *up = nullptr;       // [np_total]      carrier at x^n in record order (FP64)
     int32_t *sl = nullptr;       // [np_total]      record slot of each particle
+    // grid terms of the optional forces, in record order (allocated when a box
+    // turns on the Faxen term, the added mass or Heun): [kAux][np_total] of
+    // lap u, grad u (3: d_x u, d_y u, d_z u), carrier and lap u at Heun's x*
+    double4 *aux = nullptr;
+    double4 *vrec = nullptr;     // [np_total]      v^n in record order (Heun)
     // ERPP_F64_PLAIN
     double *pamp = nullptr;      // [4][np_total] -D/rho_f (3 components) and Z
     double *pphi = nullptr;      // [3][np_total] offsets inside the base cell
@@ -150,7 +156,8 @@ hipError_t plain_update_stage(erpp_plan *p, hipStream_t st);
 hipError_t set_step(erpp_plan *p, int64_t n, hipStream_t st);
 hipError_t advance_step(erpp_plan *p, hipStream_t st);
 hipError_t mark_added_mass(erpp_plan *p, hipStream_t st);  // after an update: history present
-bool fill_box_tiles(erpp_plan *p);          // tiles, blocks, LDS layout; false if it does not fit
+bool fill_box_tiles(erpp_plan *p);
+erpp_status ensure_aux(erpp_plan *p);   // allocate Scratch::aux / vrec (FP32 path)          // tiles, blocks, LDS layout; false if it does not fit
 // start = exclusive scan of count, count = 0; with stepp, also step[1] = step[0]++
 hipError_t scan_counts(int32_t *count, int64_t n, int32_t *start, int32_t *part, int32_t *ticket,
                        int64_t *stepp, hipStream_t st);

@@ -196,7 +196,8 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
                                                  const int32_t *__restrict__ rank,
                                                  float4 *__restrict__ rec,
                                                  double4 *__restrict__ xs,
-                                                 int32_t *__restrict__ sl) {
+                                                 int32_t *__restrict__ sl,
+                                                 double4 *__restrict__ vrec) {
     __shared__ float sP[kMaxOff + 1][kBlock];   // prefix sums of the x factors
     __shared__ int s_rng[kMaxOff];               // per mz: reachable my in [lo, hi]
     const int64_t n = *stepp;
@@ -298,6 +299,8 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
     rec[2 * slotr + 1] = make_float4(ax, ay, az, __int_as_float((int)p));
     // the current position x^n, in record order for the carrier gather
     xs[slotr] = make_double4(x0, x1, x2, 0.0);
+    // and v^n for Heun's second stage (x* = x^n + dt v^n), evaluated by the gather
+    if (vrec && B.integ == 2) vrec[slotr] = make_double4(B.v[p], B.v[np + p], B.v[2 * np + p], 0.0);
     sl[B.poff + p] = (int32_t)slotr;
 }
 
@@ -784,11 +787,19 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
 // field streams through L2 about once, instead of eight scattered rows per
 // particle.  x^n arrives in record order from the evaluation kernel; the FP64
 // trilinear value (plus the mean shear) is stored in record order too.
+// LAP: also lap u at x^n (Faxen term, added mass); GRAD: grad u at x^n (added
+// mass); HEUN: the carrier (and, with LAP, lap u) at Heun's x* = x^n + dt v^n.
+// These go to aux[k][record], k = 0 lap, 1..3 grad (d_x u, d_y u, d_z u), 4 u(x*),
+// 5 lap u(x*), for the boxes that use them.
+template <bool LAP, bool GRAD, bool HEUN>
 __global__ void __launch_bounds__(kBlock) k_gather_sorted(const DevBox *__restrict__ Bs, int nbox,
                                                           int64_t nblk,
                                                           const int64_t *__restrict__ stepp,
                                                           int M, const double4 *__restrict__ xs,
-                                                          double4 *__restrict__ up) {
+                                                          double4 *__restrict__ up,
+                                                          double4 *__restrict__ aux, int64_t npt,
+                                                          const double4 *__restrict__ vrec,
+                                                          double dt) {
     const int64_t n = *stepp;
     if (n < M) return;
     // workgroups are dealt to the 8 XCDs round-robin; give each XCD (its own L2)
@@ -806,7 +817,33 @@ __global__ void __launch_bounds__(kBlock) k_gather_sorted(const DevBox *__restri
     double xp[3] = {x4.x, x4.y, x4.z};
     double u[3];
     trilinear<float>(B, (const float *)B.u, xp, u);
-    up[B.poff + r] = make_double4(u[0], u[1], u[2], 0.0);
+    const int64_t slot = B.poff + r;
+    up[slot] = make_double4(u[0], u[1], u[2], 0.0);
+    const bool lap = LAP && (B.fax != 0.0 || B.am_mf != 0.0);
+    if (lap) {
+        double l[3];
+        trilinear_laplacian<float>(B, (const float *)B.u, xp, l);
+        aux[slot] = make_double4(l[0], l[1], l[2], 0.0);
+    }
+    if (GRAD && B.am_mf != 0.0) {
+        double g[9];
+        trilinear_gradient<float>(B, (const float *)B.u, xp, g);
+        // column j of the gradient: (d_j u_x, d_j u_y, d_j u_z)
+        for (int j = 0; j < 3; ++j)
+            aux[(1 + j) * npt + slot] = make_double4(g[j], g[3 + j], g[6 + j], 0.0);
+    }
+    if (HEUN && B.integ == 2) {
+        const double4 v4 = vrec[slot];
+        const double x2[3] = {xp[0] + dt * v4.x, xp[1] + dt * v4.y, xp[2] + dt * v4.z};
+        double u2[3];
+        trilinear<float>(B, (const float *)B.u, x2, u2);
+        aux[4 * npt + slot] = make_double4(u2[0], u2[1], u2[2], 0.0);
+        if (lap) {
+            double l2[3];
+            trilinear_laplacian<float>(B, (const float *)B.u, x2, l2);
+            aux[5 * npt + slot] = make_double4(l2[0], l2[1], l2[2], 0.0);
+        }
+    }
 }
 
 // Self term of particle p at position pos (the App. E disturbance of the last
@@ -814,7 +851,8 @@ __global__ void __launch_bounds__(kBlock) k_gather_sorted(const DevBox *__restri
 // fax lap u, vs gets fax lap v_self.
 template <bool FAX>
 __device__ __forceinline__ void self_terms(const DevBox &B, int64_t p, int64_t n, int M, int selfc,
-                                           const double pos[3], double up[3], double vs[3]) {
+                                           const double pos[3], double up[3], double vs[3],
+                                           const double (&lu_pre)[3], bool use_pre) {
     const int64_t np = B.np;
     vs[0] = vs[1] = vs[2] = 0.0;
     const bool live = selfc && n >= M + 1;
@@ -838,7 +876,11 @@ __device__ __forceinline__ void self_terms(const DevBox &B, int64_t p, int64_t n
     if (FAX && B.fax != 0.0) {
         // Faxen term (a_p^2/6) lap u~: grid Laplacian minus the self part
         double lu[3], ls[3] = {0.0, 0.0, 0.0};
-        trilinear_laplacian<float>(B, (const float *)B.u, pos, lu);
+        if (use_pre) {
+            for (int d = 0; d < 3; ++d) lu[d] = lu_pre[d];
+        } else {
+            trilinear_laplacian<float>(B, (const float *)B.u, pos, lu);
+        }
         if (live) {
             double r[3], D[3];
             for (int d = 0; d < 3; ++d) {
@@ -860,12 +902,16 @@ __device__ __forceinline__ void self_terms(const DevBox &B, int64_t p, int64_t n
 // integrator (second stage at x* = x^n + dt v^n).  Their extra work doubles the
 // registers, so plans without them run the lean instance.
 // Laplacian and gradient of u~ = u - v_self at pos for the added-mass terms:
-// interpolated nodal stencils of the carrier minus the closed forms of the
+// interpolated nodal stencils of the carrier (computed here unless pre, when
+// the caller passes them in lap and grad) minus the closed forms of the
 // self-disturbance of the last injection (FP64).
 __device__ __forceinline__ void am_terms(const DevBox &B, int64_t p, int64_t n, int M, int selfc,
-                                         const double pos[3], double lap[3], double grad[9]) {
-    trilinear_laplacian<float>(B, (const float *)B.u, pos, lap);
-    trilinear_gradient<float>(B, (const float *)B.u, pos, grad);
+                                         const double pos[3], double lap[3], double grad[9],
+                                         bool pre) {
+    if (!pre) {
+        trilinear_laplacian<float>(B, (const float *)B.u, pos, lap);
+        trilinear_gradient<float>(B, (const float *)B.u, pos, grad);
+    }
     if (selfc && n >= M + 1) {
         const int64_t np = B.np;
         const int64_t ss = (n - 1 - M) % (M + 1);
@@ -892,7 +938,8 @@ __global__ void __launch_bounds__(kBlock) k_update(const DevBox *__restrict__ Bs
                                                    const int64_t *__restrict__ stepp, int M,
                                                    double dt, int selfc,
                                                    const double4 *__restrict__ upc,
-                                                   const int32_t *__restrict__ sl) {
+                                                   const int32_t *__restrict__ sl,
+                                                   const double4 *__restrict__ aux, int64_t npt) {
     const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_p; });
     const DevBox &B = Bs[bi];
     const int64_t p = (int64_t)(blockIdx.x - B.blk_p) * kBlock + threadIdx.x;
@@ -901,33 +948,67 @@ __global__ void __launch_bounds__(kBlock) k_update(const DevBox *__restrict__ Bs
     const int64_t np = B.np;
     double xp[3] = {B.x[p], B.x[np + p], B.x[2 * np + p]};
     double up[3];
-    if (n >= M) {
-        // gathered in record order by k_gather_sorted
-        const double4 g = upc[sl[B.poff + p]];
+    // grid terms gathered in record order by k_gather_sorted once records exist;
+    // the first M steps (no records yet) interpolate in place
+    const bool rec = n >= M;
+    const int64_t sr = rec ? (int64_t)sl[B.poff + p] : 0;
+    if (rec) {
+        const double4 g = upc[sr];
         up[0] = g.x;
         up[1] = g.y;
         up[2] = g.z;
     } else {
         trilinear<float>(B, (const float *)B.u, xp, up);
     }
+    const bool lpre = (FAX || AM) && rec && (B.fax != 0.0 || B.am_mf != 0.0);
+    double lu[3] = {0.0, 0.0, 0.0};
+    if (lpre) {
+        const double4 l = aux[sr];
+        lu[0] = l.x;
+        lu[1] = l.y;
+        lu[2] = l.z;
+    }
     const int64_t sw = n % (M + 1);
     if (AM && B.am_mf != 0.0) {
         double vs[3], ut[3], lap[3], grad[9];
-        self_terms<false>(B, p, n, M, selfc, xp, up, vs);
+        self_terms<false>(B, p, n, M, selfc, xp, up, vs, lu, false);
         for (int d = 0; d < 3; ++d) ut[d] = up[d] - vs[d];
-        am_terms(B, p, n, M, selfc, xp, lap, grad);
+        if (rec) {
+            for (int d = 0; d < 3; ++d) lap[d] = lu[d];
+            for (int j = 0; j < 3; ++j) {
+                const double4 g = aux[(1 + j) * npt + sr];
+                grad[j] = g.x;
+                grad[3 + j] = g.y;
+                grad[6 + j] = g.z;
+            }
+        }
+        am_terms(B, p, n, M, selfc, xp, lap, grad, rec);
         update_particle_am(B, p, dt, xp, ut, lap, grad, *B.am_valid, B.ring_x + sw * 3 * np,
                            nullptr, (float *)B.ring_d + sw * 3 * np);
         return;
     }
     double vs[3];
-    self_terms<FAX>(B, p, n, M, selfc, xp, up, vs);
+    self_terms<FAX>(B, p, n, M, selfc, xp, up, vs, lu, lpre);
     double up2[3] = {0.0, 0.0, 0.0}, vs2[3] = {0.0, 0.0, 0.0};
     if (HEUN && B.integ == 2) {
         const double xs[3] = {xp[0] + dt * B.v[p], xp[1] + dt * B.v[np + p],
                               xp[2] + dt * B.v[2 * np + p]};
-        trilinear<float>(B, (const float *)B.u, xs, up2);
-        self_terms<FAX>(B, p, n, M, selfc, xs, up2, vs2);
+        double l2[3] = {0.0, 0.0, 0.0};
+        if (rec) {
+            const double4 g = aux[4 * npt + sr];
+            up2[0] = g.x;
+            up2[1] = g.y;
+            up2[2] = g.z;
+            if (lpre) {
+                const double4 l = aux[5 * npt + sr];
+                l2[0] = l.x;
+                l2[1] = l.y;
+                l2[2] = l.z;
+            }
+        } else {
+            trilinear<float>(B, (const float *)B.u, xs, up2);
+        }
+        self_terms<FAX>(B, p, n, M, selfc, xs, up2, vs2, l2, lpre);
     }
     update_particle(B, p, dt, xp, up, vs, up2, vs2, B.ring_x + sw * 3 * np, nullptr,
                     (float *)B.ring_d + sw * 3 * np);
@@ -1025,7 +1106,7 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
             if (P->np_total > 0)
                 hipLaunchKernelGGL(k_eval, dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step + 1, P->M, P->s.start, P->s.rank,
-                                   P->s.rec, P->s.xs, P->s.sl);
+                                   P->s.rec, P->s.xs, P->s.sl, P->s.vrec);
             break;
         case 3:
             {
@@ -1054,16 +1135,22 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
         case 4:
             if (P->np_total > 0) {
                 const int64_t grid = (P->pblocks + kXcds - 1) / kXcds * kXcds;
-                hipLaunchKernelGGL(k_gather_sorted, dim3((unsigned)grid), dim3(kBlock), 0, st,
-                                   P->dbox, P->nbox, P->pblocks, P->s.step + 1, P->M, P->s.xs,
-                                   P->s.up);
                 bool fax = false, heun = false, am = false;
                 for (const auto &B : P->hbox) {
                     fax = fax || B.fax != 0.0;
                     heun = heun || B.integ == 2;
                     am = am || B.am_mf != 0.0;
                 }
+                const bool lap = fax || am;
                 // added mass runs with explicit Euler only (checked by the setters)
+                auto gat = am ? k_gather_sorted<true, true, false>
+                         : lap ? (heun ? k_gather_sorted<true, false, true>
+                                       : k_gather_sorted<true, false, false>)
+                               : (heun ? k_gather_sorted<false, false, true>
+                                       : k_gather_sorted<false, false, false>);
+                hipLaunchKernelGGL(gat, dim3((unsigned)grid), dim3(kBlock), 0, st, P->dbox,
+                                   P->nbox, P->pblocks, P->s.step + 1, P->M, P->s.xs, P->s.up,
+                                   P->s.aux, P->np_total, P->s.vrec, P->dt);
                 auto upd = am ? (fax ? k_update<true, false, true> : k_update<false, false, true>)
                          : fax ? (heun ? k_update<true, true, false> : k_update<true, false, false>)
                                : (heun ? k_update<false, true, false>
@@ -1071,7 +1158,7 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                 hipLaunchKernelGGL(upd,
                                    dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step + 1, P->M, P->dt, P->self_correction,
-                                   P->s.up, P->s.sl);
+                                   P->s.up, P->s.sl, P->s.aux, P->np_total);
                 if (am) return mark_added_mass(P, st);
             }
             break;
