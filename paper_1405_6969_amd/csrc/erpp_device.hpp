@@ -249,44 +249,82 @@ __device__ __forceinline__ void trilinear(const DevBox &B, const T *__restrict__
 // index i in [-1, N] taken periodically into [0, N)
 __device__ __forceinline__ int wrap_node(int i, int N) { return i < 0 ? i + N : (i >= N ? i - N : i); }
 
-// Trilinear interpolation at xp of the 7-point nodal Laplacian of u (the grid
-// part of the Faxen term); the mean shear is linear and adds nothing.  FP64.
-template <typename T>
-__device__ void trilinear_laplacian(const DevBox &B, const T *__restrict__ u, const double xp[3],
-                                    double out[3]) {
+// Trilinear interpolation at xp of the 7-point nodal Laplacian of u (LAP: the
+// grid part of the Faxen term; the mean shear is linear and adds nothing) and of
+// its central-difference nodal gradient (GRAD, grad[3c + j] = d u_c / d x_j, plus
+// the mean shear's d U_x / d y).  Both stencils read the 2x2x2 cell corners and
+// their 24 face neighbours: 32 nodes per component, each loaded once.  FP64.
+template <typename T, bool LAP, bool GRAD>
+__device__ void trilinear_stencils(const DevBox &B, const T *__restrict__ u, const double xp[3],
+                                   double lap[3], double grad[9]) {
     int b[3];
     double ph[3];
     for (int d = 0; d < 3; ++d) cell_of(xp[d], B.L[d], B.dx[d], B.n[d], b[d], ph[d]);
     const int Nx = B.n[0], Ny = B.n[1], Nz = B.n[2];
     const int64_t ng = (int64_t)Nx * Ny * Nz;
+    int ix[4], iy[4], iz[4];   // nodes b - 1 .. b + 2
+    for (int q = 0; q < 4; ++q) {
+        ix[q] = wrap_node(b[0] + q - 1, Nx);
+        iy[q] = wrap_node(b[1] + q - 1, Ny);
+        iz[q] = wrap_node(b[2] + q - 1, Nz);
+    }
     const double h0 = 1.0 / (B.dx[0] * B.dx[0]), h1 = 1.0 / (B.dx[1] * B.dx[1]),
                  h2 = 1.0 / (B.dx[2] * B.dx[2]);
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int c2 = 0; c2 < 2; ++c2)
-        for (int c1 = 0; c1 < 2; ++c1)
-            for (int c0 = 0; c0 < 2; ++c0) {
-                const double w = (c0 ? ph[0] : 1.0 - ph[0]) * (c1 ? ph[1] : 1.0 - ph[1]) *
-                                 (c2 ? ph[2] : 1.0 - ph[2]);
-                const int i = wrap_node(b[0] + c0, Nx), j = wrap_node(b[1] + c1, Ny),
-                          k = wrap_node(b[2] + c2, Nz);
-                const int im = wrap_node(i - 1, Nx), ip = wrap_node(i + 1, Nx);
-                const int jm = wrap_node(j - 1, Ny), jp = wrap_node(j + 1, Ny);
-                const int km = wrap_node(k - 1, Nz), kp = wrap_node(k + 1, Nz);
-                const int64_t row = ((int64_t)k * Ny + j) * Nx;
-                for (int c = 0; c < 3; ++c) {
-                    const T *uc = u + c * ng;
-                    const double u0 = (double)uc[row + i];
-                    const double lx = ((double)uc[row + ip] - 2.0 * u0 + (double)uc[row + im]) * h0;
-                    const double ly = ((double)uc[((int64_t)k * Ny + jp) * Nx + i] - 2.0 * u0 +
-                                       (double)uc[((int64_t)k * Ny + jm) * Nx + i]) * h1;
-                    const double lz = ((double)uc[((int64_t)kp * Ny + j) * Nx + i] - 2.0 * u0 +
-                                       (double)uc[((int64_t)km * Ny + j) * Nx + i]) * h2;
-                    acc[c] += w * (lx + ly + lz);
+    const double g0 = 0.5 / B.dx[0], g1 = 0.5 / B.dx[1], g2 = 0.5 / B.dx[2];
+    for (int c = 0; c < 3; ++c) {
+        const T *uc = u + c * ng;
+        auto at = [&](int a, int bb, int cc) -> double {
+            return (double)uc[((int64_t)iz[cc] * Ny + iy[bb]) * Nx + ix[a]];
+        };
+        double cube[2][2][2], xn[2][2][2], yn[2][2][2], zn[2][2][2];
+        for (int k = 0; k < 2; ++k)
+            for (int j = 0; j < 2; ++j)
+                for (int i = 0; i < 2; ++i) cube[i][j][k] = at(1 + i, 1 + j, 1 + k);
+        for (int s2 = 0; s2 < 2; ++s2)
+            for (int t = 0; t < 2; ++t) {
+                // the neighbour outside the cube: index 0 (s = 0) or 3 (s = 1)
+                for (int s = 0; s < 2; ++s) {
+                    xn[s][s2][t] = at(3 * s, 1 + s2, 1 + t);
+                    yn[s][s2][t] = at(1 + s2, 3 * s, 1 + t);
+                    zn[s][s2][t] = at(1 + s2, 1 + t, 3 * s);
                 }
             }
-    out[0] = acc[0];
-    out[1] = acc[1];
-    out[2] = acc[2];
+        double accl = 0.0, accg[3] = {0.0, 0.0, 0.0};
+        for (int c2 = 0; c2 < 2; ++c2)
+            for (int c1 = 0; c1 < 2; ++c1)
+                for (int c0 = 0; c0 < 2; ++c0) {
+                    const double w = (c0 ? ph[0] : 1.0 - ph[0]) * (c1 ? ph[1] : 1.0 - ph[1]) *
+                                     (c2 ? ph[2] : 1.0 - ph[2]);
+                    const double u0 = cube[c0][c1][c2];
+                    const double xm = c0 ? cube[0][c1][c2] : xn[0][c1][c2];
+                    const double xq = c0 ? xn[1][c1][c2] : cube[1][c1][c2];
+                    const double ym = c1 ? cube[c0][0][c2] : yn[0][c0][c2];
+                    const double yq = c1 ? yn[1][c0][c2] : cube[c0][1][c2];
+                    const double zm = c2 ? cube[c0][c1][0] : zn[0][c0][c1];
+                    const double zq = c2 ? zn[1][c0][c1] : cube[c0][c1][1];
+                    if (LAP) {
+                        const double lx = (xq - 2.0 * u0 + xm) * h0;
+                        const double ly = (yq - 2.0 * u0 + ym) * h1;
+                        const double lz = (zq - 2.0 * u0 + zm) * h2;
+                        accl += w * (lx + ly + lz);
+                    }
+                    if (GRAD) {
+                        accg[0] += w * ((xq - xm) * g0);
+                        accg[1] += w * ((yq - ym) * g1);
+                        accg[2] += w * ((zq - zm) * g2);
+                    }
+                }
+        if (LAP) lap[c] = accl;
+        if (GRAD)
+            for (int j = 0; j < 3; ++j) grad[3 * c + j] = accg[j];
+    }
+    if (GRAD) grad[1] += B.shear;
+}
+
+template <typename T>
+__device__ __forceinline__ void trilinear_laplacian(const DevBox &B, const T *__restrict__ u,
+                                                    const double xp[3], double out[3]) {
+    trilinear_stencils<T, true, false>(B, u, xp, out, nullptr);
 }
 
 // Laplacian of the closed-form self-disturbance (the self part of the Faxen
@@ -343,42 +381,6 @@ __device__ __forceinline__ void self_gradient64(const double r[3], const double 
             if (c == j) t -= H * Dr;
             out[3 * c + j] = pref * t;
         }
-}
-
-// Trilinear interpolation at x of the central-difference nodal gradient of u,
-// out[3c + j] = d u_c / d x_j, plus the mean shear's d U_x / d y.
-template <typename T>
-__device__ void trilinear_gradient(const DevBox &B, const T *__restrict__ u, const double xp[3],
-                                   double out[9]) {
-    int b[3];
-    double ph[3];
-    for (int d = 0; d < 3; ++d) cell_of(xp[d], B.L[d], B.dx[d], B.n[d], b[d], ph[d]);
-    const int Nx = B.n[0], Ny = B.n[1], Nz = B.n[2];
-    const int64_t ng = (int64_t)Nx * Ny * Nz;
-    const double h[3] = {0.5 / B.dx[0], 0.5 / B.dx[1], 0.5 / B.dx[2]};
-    double acc[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int c2 = 0; c2 < 2; ++c2)
-        for (int c1 = 0; c1 < 2; ++c1)
-            for (int c0 = 0; c0 < 2; ++c0) {
-                const double w = (c0 ? ph[0] : 1.0 - ph[0]) * (c1 ? ph[1] : 1.0 - ph[1]) *
-                                 (c2 ? ph[2] : 1.0 - ph[2]);
-                const int i = wrap_node(b[0] + c0, Nx), j = wrap_node(b[1] + c1, Ny),
-                          k = wrap_node(b[2] + c2, Nz);
-                const int64_t xm = ((int64_t)k * Ny + j) * Nx + wrap_node(i - 1, Nx);
-                const int64_t xq = ((int64_t)k * Ny + j) * Nx + wrap_node(i + 1, Nx);
-                const int64_t ym = ((int64_t)k * Ny + wrap_node(j - 1, Ny)) * Nx + i;
-                const int64_t yq = ((int64_t)k * Ny + wrap_node(j + 1, Ny)) * Nx + i;
-                const int64_t zm = ((int64_t)wrap_node(k - 1, Nz) * Ny + j) * Nx + i;
-                const int64_t zq = ((int64_t)wrap_node(k + 1, Nz) * Ny + j) * Nx + i;
-                for (int c = 0; c < 3; ++c) {
-                    const T *uc = u + c * ng;
-                    acc[3 * c + 0] += w * (((double)uc[xq] - (double)uc[xm]) * h[0]);
-                    acc[3 * c + 1] += w * (((double)uc[yq] - (double)uc[ym]) * h[1]);
-                    acc[3 * c + 2] += w * (((double)uc[zq] - (double)uc[zm]) * h[2]);
-                }
-            }
-    acc[1] += B.shear;
-    for (int q = 0; q < 9; ++q) out[q] = acc[q];
 }
 
 // History write, position wrap (Lees-Edwards velocity jump in y when a mean

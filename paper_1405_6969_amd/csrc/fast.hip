@@ -820,14 +820,16 @@ __global__ void __launch_bounds__(kBlock) k_gather_sorted(const DevBox *__restri
     const int64_t slot = B.poff + r;
     up[slot] = make_double4(u[0], u[1], u[2], 0.0);
     const bool lap = LAP && (B.fax != 0.0 || B.am_mf != 0.0);
-    if (lap) {
-        double l[3];
-        trilinear_laplacian<float>(B, (const float *)B.u, xp, l);
-        aux[slot] = make_double4(l[0], l[1], l[2], 0.0);
-    }
-    if (GRAD && B.am_mf != 0.0) {
-        double g[9];
-        trilinear_gradient<float>(B, (const float *)B.u, xp, g);
+    const bool grad = GRAD && B.am_mf != 0.0;
+    double l[3], g[9];
+    if (lap && grad)
+        trilinear_stencils<float, true, true>(B, (const float *)B.u, xp, l, g);
+    else if (lap)
+        trilinear_stencils<float, true, false>(B, (const float *)B.u, xp, l, g);
+    else if (grad)
+        trilinear_stencils<float, false, true>(B, (const float *)B.u, xp, l, g);
+    if (lap) aux[slot] = make_double4(l[0], l[1], l[2], 0.0);
+    if (grad) {
         // column j of the gradient: (d_j u_x, d_j u_y, d_j u_z)
         for (int j = 0; j < 3; ++j)
             aux[(1 + j) * npt + slot] = make_double4(g[j], g[3 + j], g[6 + j], 0.0);
@@ -908,10 +910,7 @@ __device__ __forceinline__ void self_terms(const DevBox &B, int64_t p, int64_t n
 __device__ __forceinline__ void am_terms(const DevBox &B, int64_t p, int64_t n, int M, int selfc,
                                          const double pos[3], double lap[3], double grad[9],
                                          bool pre) {
-    if (!pre) {
-        trilinear_laplacian<float>(B, (const float *)B.u, pos, lap);
-        trilinear_gradient<float>(B, (const float *)B.u, pos, grad);
-    }
+    if (!pre) trilinear_stencils<float, true, true>(B, (const float *)B.u, pos, lap, grad);
     if (selfc && n >= M + 1) {
         const int64_t np = B.np;
         const int64_t ss = (n - 1 - M) % (M + 1);

@@ -154,8 +154,7 @@ __device__ void plain_am_terms(const DevBox &B, int64_t p, int64_t n, int M, int
     const int64_t np = B.np;
     const double *u = (const double *)B.u;
     trilinear<double>(B, u, pos, ut);
-    trilinear_laplacian<double>(B, u, pos, lap);
-    trilinear_gradient<double>(B, u, pos, grad);
+    trilinear_stencils<double, true, true>(B, u, pos, lap, grad);
     if (selfc && n >= M + 1) {
         const int64_t ss = (n - 1 - M) % (M + 1);
         const double *Xs = B.ring_x + ss * 3 * np;
