@@ -180,12 +180,12 @@ erpp_status erpp_plan_set_faxen(erpp_plan *plan, int32_t ibox, double a_p);
 erpp_status erpp_plan_set_added_mass(erpp_plan *plan, int32_t ibox, double a, double *hist);
 
 /* Particle integrator of every box (default ERPP_EULER).  The self-disturbance
- * removed from u~ is the same App. E closed form for both (the fluid receives
- * one forcing step of the handed-over drag either way; Heun removes it at
+ * removed from u~ is the same App. E closed form for all three (the fluid
+ * receives one forcing step of the handed-over drag in each; Heun removes it at
  * each stage's position).  Applies to later steps; invalidates captured graphs.
- * Synchronises the device.  ERPP_EINVAL for a bad plan or kind, or Heun with a
- * sheared box; ERPP_EUNSUPPORTED for another integrator than Euler while a box
- * has the added-mass terms on. */
+ * Synchronises the device.  ERPP_EINVAL for a bad plan or kind;
+ * ERPP_EUNSUPPORTED for Heun while a box has a mean shear, or for another
+ * integrator than Euler while a box has the added-mass terms on. */
 erpp_status erpp_plan_set_integrator(erpp_plan *plan, erpp_integrator kind);
 
 /* Autotuner (ERPP_F32_FAST): times every candidate pencil shape on the plan's own

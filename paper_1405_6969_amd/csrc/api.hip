@@ -526,8 +526,8 @@ erpp_status erpp_plan_set_integrator(erpp_plan *p, erpp_integrator kind) {
     if (kind == ERPP_HEUN)
         for (int32_t b = 0; b < p->nbox; ++b)
             if (p->boxes[b].shear != 0.0)
-                return fail(ERPP_EINVAL, "box %d: Heun needs shear = 0 (its second stage would "
-                                         "straddle the Lees-Edwards jump)", b);
+                return fail(ERPP_EUNSUPPORTED, "box %d: Heun needs shear = 0 (its second "
+                                               "stage would straddle the Lees-Edwards jump)", b);
     if (kind == ERPP_HEUN) {
         erpp_status s = erpp::ensure_aux(p);
         if (s != ERPP_OK) return s;

@@ -117,18 +117,21 @@ def test_added_mass_rejections():
                              shear=1.0, seed=workloads.SEED_BASE + 7)
     db = upload(workloads.make_box(spec), 2, erpp.F32_FAST)
     with erpp.Plan([db], 2, 1e-3) as plan:
-        with pytest.raises(erpp.ErppError):
+        with pytest.raises(erpp.ErppError) as e:
             plan.set_added_mass(0, 0.1)
+        assert e.value.status == erpp.ERPP_EUNSUPPORTED
     box = _box(203, n=(16, 16, 16), np_=50)
     db = upload(box, 2, erpp.F32_FAST)
     with erpp.Plan([db], 2, 1e-3) as plan:
         plan.set_integrator(erpp.EXPONENTIAL)
-        with pytest.raises(erpp.ErppError):
+        with pytest.raises(erpp.ErppError) as e:
             plan.set_added_mass(0, 0.1)
+        assert e.value.status == erpp.ERPP_EUNSUPPORTED
         plan.set_integrator(erpp.EULER)
         plan.set_added_mass(0, 0.1)
-        with pytest.raises(erpp.ErppError):
+        with pytest.raises(erpp.ErppError) as e:
             plan.set_integrator(erpp.HEUN)
+        assert e.value.status == erpp.ERPP_EUNSUPPORTED
         lib = erpp.load()
         assert lib.erpp_plan_set_added_mass(plan.h, 0, C.c_double(0.1), None) == erpp.ERPP_EINVAL
         plan.set_added_mass(0, 0.0)

@@ -322,6 +322,7 @@ def test_heun_rejects_sheared_box():
                              placement="uniform", shear=1.0, seed=workloads.SEED_BASE + 5)
     db = upload(workloads.make_box(spec), 2, erpp.F32_FAST)
     with erpp.Plan([db], 2, 1e-3) as plan:
-        with pytest.raises(erpp.ErppError):
+        with pytest.raises(erpp.ErppError) as e:
             plan.set_integrator(erpp.HEUN)
+        assert e.value.status == erpp.ERPP_EUNSUPPORTED
         plan.set_integrator(erpp.EXPONENTIAL)
