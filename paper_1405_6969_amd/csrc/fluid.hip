@@ -363,9 +363,19 @@ __global__ __launch_bounds__(256) void k_fy(cplx<T> *__restrict__ U, int nslab, 
     }
 }
 
+// Logical block of a launch whose grid is padded to a multiple of kXcds:
+// physical block b runs on XCD b mod kXcds; XCD x takes logical blocks
+// [x G/kXcds, (x + 1) G/kXcds), in order.  A bijection on [0, grid).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int grid) {
+    return (b % kXcds) * (grid / kXcds) + b / kXcds;
+}
+
 // Pass 3: for one ky and TX consecutive kx, the z lines of all three
 // components: forward transform along z, the Fourier multiplier of the step
 // (as in k_fluid_spectral, which holds the Nyquist rule), inverse transform.
+// A tile narrower than a cache line shares each line with the next tile, so
+// consecutive tiles are kept on one XCD (its own L2), one after the other.
 constexpr int kZThreads = 512;
 constexpr int kZVpt = 8;       // values per thread of the z pass
 
@@ -380,7 +390,9 @@ __global__ __launch_bounds__(kZThreads) void k_fz_spec(cplx<T> *__restrict__ U, 
     const int nx = 1 << lognx, ny = 1 << logny, nz = 1 << lognz, tx = 1 << logtx;
     const int nkx = nx / 2 + 1, ld = nz + 1;
     const int ntile = (nkx + tx - 1) >> logtx;
-    const int iy = blockIdx.x / ntile, tile = blockIdx.x - iy * ntile;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    if (blk >= ny * ntile) return;       // grid padding
+    const int iy = blk / ntile, tile = blk - iy * ntile;
     const int kx0 = tile << logtx;
     const int w = min(tx, nkx - kx0);
     const int64_t zstride = (int64_t)ny * rs, cstride = (int64_t)nz * zstride;
@@ -516,7 +528,7 @@ hipError_t launch_own(erpp_fluid *fl, T *u, const T *f, hipStream_t st) {
     // pass 3: along z, the Fourier multiplier, back along z
     const int txz = tile_width((size_t)3 * (nz + 1) * cs, kFftLds, (size_t)3 * nz, (size_t)kZVpt * kZThreads);
     const int logtxz = ilog2(txz);
-    const unsigned gz = (unsigned)(ny * ((nkx + txz - 1) / txz));
+    const unsigned gz = (unsigned)((ny * ((nkx + txz - 1) / txz) + kXcds - 1) / kXcds * kXcds);
     const double tp = 2.0 * M_PI;
     hipLaunchKernelGGL(k_fz_spec<T>, dim3(gz), dim3(kZThreads), (size_t)3 * txz * (nz + 1) * cs, st, U,
                        lognx, logny, lognz, rs, logtxz, (T)(tp / fl->L[0]), (T)(tp / fl->L[1]),
