@@ -189,10 +189,14 @@ erpp_status erpp_plan_set_added_mass(erpp_plan *plan, int32_t ibox, double a, do
 erpp_status erpp_plan_set_integrator(erpp_plan *plan, erpp_integrator kind);
 
 /* Autotuner (ERPP_F32_FAST): times every candidate pencil shape on the plan's own
- * boxes (scatter of the current ring contents, which are only read) and keeps
- * the fastest.  With cache_path != NULL the choice is read from / appended to
- * that text file, keyed by the geometry; a hit skips the timing.  Synchronises
- * `stream`.  On ERPP_F64_PLAIN plans it is a no-op. */
+ * boxes with the scatter of step n, the step following the last one run (the
+ * ring, positions and velocities are only read) and keeps the fastest.
+ * Afterwards the step counter is n again and every box's f holds the forcing of
+ * step n, which the next erpp_step(n) writes again.  With cache_path != NULL the
+ * choice is read from / appended to that text file, keyed by the geometry; a
+ * hit skips the timing.  Synchronises `stream`.  ERPP_EINVAL when fewer than M
+ * steps have run and the cache has no entry (the scatter of step n reads ring
+ * level n - M).  On ERPP_F64_PLAIN plans it is a no-op. */
 erpp_status erpp_plan_tune(erpp_plan *plan, const char *cache_path, void *stream);
 
 /* Number of bins of box `ibox` for erpp_bin: its grid cells, Nx * Ny * Nz. */

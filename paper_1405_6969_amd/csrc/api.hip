@@ -730,10 +730,18 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
     hipEvent_t a, b;
     HIP_OR_RETURN(hipEventCreate(&a));
     HIP_OR_RETURN(hipEventCreate(&b));
-    // the scatter reads ring level n-M; use the step following the last one run
+    // the scatter reads ring level n-M of the step n following the last one run;
+    // before M steps that level has not been written
     int64_t n = 0;
+    HIP_OR_RETURN(hipStreamSynchronize(st));
     HIP_OR_RETURN(hipMemcpy(&n, p->s.step, sizeof n, hipMemcpyDeviceToHost));
-    if (n < p->M) n = p->M;
+    if (n < p->M) {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return fail(ERPP_EINVAL,
+                    "erpp_plan_tune: %lld steps run, the scatter needs ring level n - M (run at "
+                    "least M = %d steps first)", (long long)n, p->M);
+    }
     erpp_status status = ERPP_OK;
     for (int c = 0; c < ncand && status == ERPP_OK; ++c) {
         if (check_tile(cand[c]) != ERPP_OK) continue;
@@ -757,8 +765,11 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    // leave the step counter where it was
-    (void)erpp::set_step(p, n, st);
+    // leave the step counter where it was (each timed scatter advanced it)
+    {
+        const hipError_t e = erpp::set_step(p, n, st);
+        if (e != hipSuccess && status == ERPP_OK) status = hip_fail(e, "erpp_plan_tune");
+    }
     if (status != ERPP_OK) return status;
     status = erpp_plan_set_tile(p, best);
     if (status == ERPP_OK && cache_path) {

@@ -310,11 +310,12 @@ __device__ __forceinline__ int wrap_index(int i, int N) {
 }
 
 // --------------------------------------------------------- scatter bound ----
-// Fixed-point range of each scatter pencil.  A node in x-block X (16 cells, at
-// least the stencil half-width) receives only from particles in x-blocks
-// X-1..X+1 of the cell rows its row classes reach, each at most max_c |a| (the
+// Fixed-point range of each scatter pencil.  A node in x-block X receives only
+// from particles whose base cell lies within the stencil's x offsets of the
+// block, in the cell rows its row classes reach, each at most max_c |a| (the
 // raw Gaussian is <= 1).  k_block_sums: for every cell row and x-block, the sum
-// of max_c |a| over the records of blocks X-1..X+1 (periodic).  k_pencil_scale:
+// of max_c |a| over the records of the blocks holding those base cells
+// (periodic; one or two runs of keys).  k_pencil_scale:
 // for every pencil, the largest sum over (pencil row, X) of those entries over
 // the reachable row classes bounds |f| on the pencil; its scale is 2^30 / bound.
 __device__ __forceinline__ float rec_amax(const float4 *__restrict__ rec, int64_t r) {
@@ -335,22 +336,41 @@ __global__ void __launch_bounds__(kBlock) k_block_sums(const DevBox *__restrict_
     if (e >= (int64_t)B.n[1] * B.n[2] * nxb) return;
     const int X = (int)(e % nxb);
     const int64_t row = B.key_off + (e - X);     // first key of the cell row
-    int g0[3], g1[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        int Xk = X + k - 1;
-        Xk += (Xk < 0) ? nxb : 0;
-        Xk -= (Xk >= nxb) ? nxb : 0;
-        g0[k] = start[row + Xk];
-        g1[k] = start[row + Xk + 1];
+    // A node x of block X receives from base cells b0 = x - m, m in [mlo, mhi]:
+    // the cells [16 X - mhi, min(16 X + 15, Nx - 1) - mlo] (periodic).  Their
+    // blocks form one run of keys, or two when the cell range wraps (a short
+    // last block can put cells of block nxb - 2 in the range of block 0).
+    const int Nx = B.n[0];
+    const int xhi = min((X << kXBlockShift) + (1 << kXBlockShift) - 1, Nx - 1);
+    int clo = (X << kXBlockShift) - B.mhi[0];
+    int chi = xhi - B.mlo[0];
+    int k0a, k0b, k1a, k1b;                       // key runs [k0a, k0b), [k1a, k1b)
+    if (chi - clo + 1 >= Nx) {
+        k0a = 0, k0b = nxb, k1a = k1b = 0;
+    } else {
+        clo = wrap_index(clo, Nx);
+        chi = wrap_index(chi, Nx);
+        const int blo = clo >> kXBlockShift, bhi = chi >> kXBlockShift;
+        if (clo <= chi) {
+            k0a = blo, k0b = bhi + 1, k1a = k1b = 0;
+        } else if (bhi >= blo) {                  // the two runs overlap: every block
+            k0a = 0, k0b = nxb, k1a = k1b = 0;
+        } else {
+            k0a = blo, k0b = nxb, k1a = 0, k1b = bhi + 1;
+        }
     }
+    int g0[2], g1[2];
+    g0[0] = start[row + k0a];
+    g1[0] = start[row + k0b];
+    g0[1] = (k1b > k1a) ? start[row + k1a] : 0;
+    g1[1] = (k1b > k1a) ? start[row + k1b] : 0;
     // Records within a key sit in an arbitrary order (atomic ranks), so the sum
     // runs in FP64, exact for FP32 terms unless their exponents spread over
     // ~29 bits, and is rounded up to FP32: the bound, and with it the
     // fixed-point scale and the forcing, do not depend on that order.
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 2; ++k)
 #pragma unroll 4
         for (int g = g0[k]; g < g1[k]; ++g) s += (double)rec_amax(rec, g);
     bsum[B.key_off + e] = __double2float_ru(s);

@@ -20,6 +20,39 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / nb)
 
 
+def forcing_errors(fg, fo):
+    """Node-by-node comparison of a GPU forcing with the oracle's: the largest
+    error over nodes and components relative to the largest oracle value, the
+    nodes where the oracle is exactly zero but the GPU is not, and the nodes
+    where the oracle exceeds 1e-6 of its largest value but the GPU is zero."""
+    fg = np.asarray(fg, dtype=np.float64)
+    fo = np.asarray(fo, dtype=np.float64)
+    mo = float(np.max(np.abs(fo))) if fo.size else 0.0
+    if mo == 0.0:
+        return (0.0 if not np.any(fg) else np.inf), int(np.count_nonzero(fg)), 0
+    err = float(np.max(np.abs(fg - fo))) / mo
+    extra = int(np.count_nonzero((fo == 0) & (fg != 0)))
+    lost = int(np.count_nonzero((np.abs(fo) > 1e-6 * mo) & (fg == 0)))
+    return err, extra, lost
+
+
+def node_tolerance(precision):
+    """Per-node bar on the forcing, relative to the largest oracle value."""
+    import paper_1405_6969_amd as erpp
+    return 1e-5 if precision == erpp.F32_FAST else 1e-12
+
+
+def assert_forcing_matches(fg, fo, precision, what=""):
+    """rel-L2 and node-by-node bars, and the same set of touched nodes."""
+    tol_f, _ = tolerances(precision)
+    e2 = rel_l2(fg, fo)
+    assert e2 <= tol_f, (what, "rel-L2", e2)
+    err, extra, lost = forcing_errors(fg, fo)
+    assert err <= node_tolerance(precision), (what, "max node error", err)
+    assert extra == 0 and lost == 0, (what, "node set", extra, lost)
+    return e2, err
+
+
 def carrier_for(box, precision):
     """The carrier both sides consume: FP32-rounded for the FP32 path."""
     import paper_1405_6969_amd as erpp
@@ -74,7 +107,9 @@ def sampled_parity(box, db, M, dt, steps, precision, rng, nsample=4000, wn=(24, 
     subset reproduces that subset exactly.  (a) v and x of `nsample` random
     particles; (b) the forcing of the last step on a node window, from every
     particle that can reach it (3 sigma plus the largest drift over the run).
-    Returns (rel-L2 of v, max periodic |dx|, rel-L2 of f on the window)."""
+    Returns (rel-L2 of v, max periodic |dx|, rel-L2 of f on the window, largest
+    node error of f on the window relative to its largest oracle value); the
+    window's touched-node set is asserted equal."""
     import torch
     P = oracle.params_for_box(box, M, dt, self_correction)
     u = carrier_for(box, precision)
@@ -100,7 +135,9 @@ def sampled_parity(box, db, M, dt, steps, precision, rng, nsample=4000, wn=(24, 
     iy = (np.arange(wn[1]) + lo[1]) % box.n[1]
     ix = (np.arange(wn[0]) + lo[0]) % box.n[0]
     fw = fg[:, iz][:, :, iy][:, :, :, ix]
-    return ev, ex, rel_l2(fw, fo)
+    err, extra, lost = forcing_errors(fw, fo)
+    assert extra == 0 and lost == 0, ("window node set", extra, lost)
+    return ev, ex, rel_l2(fw, fo), err
 
 
 # ------------------------------------------------ fluid-step helpers ----

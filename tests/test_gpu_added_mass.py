@@ -20,7 +20,8 @@ import pytest
 
 import oracle
 from oracle import fluid as ofluid
-from helpers import carrier_for, periodic_diff, rel_l2, tolerances, upload
+from helpers import (assert_forcing_matches, carrier_for, periodic_diff, rel_l2,
+                     tolerances, upload)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -68,7 +69,7 @@ def test_added_mass_step_matches_oracle(prec, faxen):
             plan.step(n)
             fo, _ = run.step(want_f=True)
             if n >= M:
-                assert rel_l2(db.f.double().cpu().numpy(), fo) <= tf, n
+                assert_forcing_matches(db.f.double().cpu().numpy(), fo, prec, n)
             assert rel_l2(db.v.cpu().numpy(), run.v) <= tv, n
         torch.cuda.synchronize()
     ex = np.max(np.abs(periodic_diff(db.x.cpu().numpy(), run.x, box.L)))

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workloads
-from helpers import sampled_parity, tolerances, upload
+from helpers import node_tolerance, sampled_parity, tolerances, upload
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -46,11 +46,12 @@ def test_full_size_sampled(cfg, prec):
     print(f"[full-size] {w.name} {prec}: {boxes[0].np_} particles, {steps} steps", flush=True)
     plan, dbs = _bench_like_run(boxes, w, p, steps)
     with plan:
-        ev, ex, ef = sampled_parity(boxes[0], dbs[0], w.M, w.dt, steps, p,
-                                    np.random.default_rng(1000 + cfg))
+        ev, ex, ef, en = sampled_parity(boxes[0], dbs[0], w.M, w.dt, steps, p,
+                                        np.random.default_rng(1000 + cfg))
     tol_f, tol_v = tolerances(p)
-    print(f"[full-size] {w.name} {prec}: rel-L2 v {ev:.2e}, |dx| {ex:.2e}, f {ef:.2e}", flush=True)
-    assert ev <= tol_v and ef <= tol_f
+    print(f"[full-size] {w.name} {prec}: rel-L2 v {ev:.2e}, |dx| {ex:.2e}, f {ef:.2e}, "
+          f"f max node {en:.2e}", flush=True)
+    assert ev <= tol_v and ef <= tol_f and en <= node_tolerance(p)
     assert ex <= (1e-9 if p == erpp.F32_FAST else 1e-12)
 
 
@@ -64,15 +65,18 @@ def test_full_size_ensemble_sampled():
     plan, dbs = _bench_like_run(boxes, w, erpp.F32_FAST, steps)
     rng = np.random.default_rng(5005)
     tol_f, tol_v = tolerances(erpp.F32_FAST)
-    worst_v = worst_f = 0.0
+    worst_v = worst_f = worst_n = 0.0
     with plan:
         for i, (b, db) in enumerate(zip(boxes, dbs)):
             with_f = i % 16 == 0
-            ev, ex, ef = sampled_parity(b, db, w.M, w.dt, steps, erpp.F32_FAST, rng, nsample=200,
-                                        wn=(16, 16, 16) if with_f else (1, 1, 1))
+            ev, ex, ef, en = sampled_parity(b, db, w.M, w.dt, steps, erpp.F32_FAST, rng,
+                                            nsample=200,
+                                            wn=(16, 16, 16) if with_f else (1, 1, 1))
             worst_v = max(worst_v, ev)
             if with_f:
                 worst_f = max(worst_f, ef)
+                worst_n = max(worst_n, en)
             assert ex <= 1e-9, (i, ex)
-    print(f"[full-size] ensemble: worst rel-L2 v {worst_v:.2e}, f {worst_f:.2e}", flush=True)
-    assert worst_v <= tol_v and worst_f <= tol_f
+    print(f"[full-size] ensemble: worst rel-L2 v {worst_v:.2e}, f {worst_f:.2e}, "
+          f"f max node {worst_n:.2e}", flush=True)
+    assert worst_v <= tol_v and worst_f <= tol_f and worst_n <= node_tolerance(erpp.F32_FAST)

@@ -147,7 +147,7 @@ def test_exponential_integrator_matches_oracle(prec):
     x within steps * dt * (v bar) * max|v| (FP32) and 1e-12 (FP64)."""
     _cuda()
     import workloads
-    from helpers import carrier_for, periodic_diff, tolerances, upload
+    from helpers import assert_forcing_matches, carrier_for, periodic_diff, tolerances, upload
     spec = workloads.BoxSpec(n=(32, 28, 24), L=(2 * math.pi, 2 * math.pi * 28 / 32,
                                                  2 * math.pi * 24 / 32), np_=1500,
                              carrier="k53", kmax=6.0, tau=(0.01, 0.05), nu=0.05,
@@ -169,7 +169,7 @@ def test_exponential_integrator_matches_oracle(prec):
             plan.step(n)
             fo, _ = run.step(want_f=True)
             if n >= M:
-                assert rel_l2(db.f.double().cpu().numpy(), fo) <= tf, n
+                assert_forcing_matches(db.f.double().cpu().numpy(), fo, prec, n)
         torch.cuda.synchronize()
     assert rel_l2(db.v.cpu().numpy(), run.v) <= tv
     # positions take dt (u~ + tau g_b) directly: the displacement the velocity bar allows
