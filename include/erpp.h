@@ -212,6 +212,22 @@ erpp_status erpp_plan_bins(const erpp_plan *plan, int32_t ibox, int32_t *nbin);
 erpp_status erpp_bin(erpp_plan *plan, int32_t ibox, const double *pos, int32_t *key,
                      int32_t *perm, int32_t *bin_start, void *stream);
 
+/* erpp_bin for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * binning of np positions of one box of n[0] x n[1] x n[2] cells and lengths L
+ * (host arrays), with no plan.  It allocates nothing: its scratch (cell
+ * histogram, ranks, scan partials) is a static device array of the library,
+ * one copy per GPU (about 16.8 MB, held until the process ends), found on the
+ * first call on each device, which must be the current device.  Limits:
+ * n[0] n[1] n[2] <= 2^21 cells and np <= 2^21 particles, else ERPP_EINVAL with
+ * nothing launched.  pos, key, perm, bin_start: device, caller-owned, sizes
+ * [3][np], np, np, ncell + 1, with the layout and results of erpp_bin.  Every
+ * call on a GPU uses that GPU's one scratch array: calls that overlap on one GPU
+ * (other streams, other host threads) race and must be ordered by the caller.
+ * Asynchronous on `stream` (a stream of the current device). */
+erpp_status erpp_bin_static(const int32_t n[3], const double L[3], int64_t np, const double *pos,
+                            int32_t *key, int32_t *perm, int32_t *bin_start, void *stream);
+
 /* Stages 1-3 for every box: write f for step `step` from ring level step-M
  * (f = 0 when step < M).  The ring is only read. */
 erpp_status erpp_scatter(erpp_plan *plan, int64_t step, void *stream);

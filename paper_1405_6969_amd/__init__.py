@@ -24,7 +24,7 @@ EXPORTS = ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile", "erpp
            "erpp_stage_times", "erpp_plan_destroy", "erpp_status_string", "erpp_last_error",
            "erpp_fluid_create", "erpp_fluid_step", "erpp_fluid_destroy", "erpp_run_coupled",
            "erpp_plan_set_body_force", "erpp_plan_set_integrator", "erpp_plan_set_faxen",
-           "erpp_plan_set_added_mass"]
+           "erpp_plan_set_added_mass", "erpp_bin_static"]
 
 
 class ErppError(RuntimeError):
@@ -83,11 +83,13 @@ def load(path: str = LIB_PATH):
     lib.erpp_plan_set_integrator.argtypes = [vp, C.c_int]
     lib.erpp_plan_set_faxen.argtypes = [vp, i32, d]
     lib.erpp_plan_set_added_mass.argtypes = [vp, i32, d, vp]
+    lib.erpp_bin_static.argtypes = [C.POINTER(i32), C.POINTER(d), i64, vp, vp, vp, vp, vp]
     for name in ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile",
                  "erpp_plan_tune", "erpp_plan_bins", "erpp_bin", "erpp_scatter", "erpp_gather",
                  "erpp_step", "erpp_run", "erpp_stage_times", "erpp_fluid_create",
                  "erpp_fluid_step", "erpp_run_coupled", "erpp_plan_set_body_force",
-                 "erpp_plan_set_integrator", "erpp_plan_set_faxen", "erpp_plan_set_added_mass"]:
+                 "erpp_plan_set_integrator", "erpp_plan_set_faxen", "erpp_plan_set_added_mass",
+                 "erpp_bin_static"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -162,6 +164,28 @@ def device_box(n, L, x, v, tau, u, M, m_p, rho_f, nu, sigma, cutoff=3.0, shear=0
                      ring_x=ring_x, ring_d=ring_d, tau=taut, u=ut, f=f, m_p=float(m_p),
                      rho_f=float(rho_f), nu=float(nu), sigma=float(sigma),
                      cutoff=float(cutoff), shear=float(shear))
+
+
+def bin_static(n, L, pos, stream=None):
+    """erpp_bin_static: exact cell binning of the [3][np] FP64 device positions
+    `pos` of one box of n cells and lengths L, with no plan and no device
+    allocation inside the library.  Returns (key, perm, bin_start) (int32 device
+    tensors allocated here by the caller side)."""
+    import torch
+    lib = load()
+    np_ = pos.shape[1]
+    dev = pos.device
+    ncell = int(n[0]) * int(n[1]) * int(n[2])
+    key = torch.empty(np_, dtype=torch.int32, device=dev)
+    perm = torch.empty(np_, dtype=torch.int32, device=dev)
+    start = torch.empty(ncell + 1, dtype=torch.int32, device=dev)
+    nn = (C.c_int32 * 3)(*[int(a) for a in n])
+    LL = (C.c_double * 3)(*[float(a) for a in L])
+    _check(lib.erpp_bin_static(nn, LL, int(np_), C.c_void_p(pos.data_ptr()),
+                               C.c_void_p(key.data_ptr()), C.c_void_p(perm.data_ptr()),
+                               C.c_void_p(start.data_ptr()), _stream(stream)),
+           "erpp_bin_static")
+    return key, perm, start
 
 
 class Plan:

@@ -68,6 +68,14 @@ struct DevBox {
     void *f;
 };
 
+// Geometry of one exact cell binning (erpp_bin), passed to its kernels by value.
+struct BinGeom {
+    int32_t n[3];
+    double L[3];
+    double dx[3];        // L / N
+    int64_t np;
+};
+
 struct Scratch {
     // ERPP_F32_FAST
     int32_t *count = nullptr;    // [ncell_total]   per-step cell histogram (kept zero at rest)
@@ -151,6 +159,12 @@ hipError_t fast_update_stage(erpp_plan *p, hipStream_t st);     // gather, self 
 hipError_t fast_gather(erpp_plan *p, double *u_p, hipStream_t st);
 hipError_t fast_bin_positions(erpp_plan *p, int ibox, const double *pos, int32_t *key,
                               int32_t *perm, int32_t *bin_start, hipStream_t st);
+// exact cell binning with caller-provided scratch: count [ncell] (zero on entry
+// unless clear), rank [np], part [ncell / kScanChunk + 2], ticket [1] (zero on
+// entry unless clear); count and ticket are zero again on exit
+hipError_t bin_positions(const BinGeom &G, const double *pos, int32_t *key, int32_t *perm,
+                         int32_t *bin_start, int32_t *count, int32_t *rank, int32_t *part,
+                         int32_t *ticket, bool clear, hipStream_t st);
 hipError_t plain_scatter_stages(erpp_plan *p, hipStream_t st);
 hipError_t plain_update_stage(erpp_plan *p, hipStream_t st);
 hipError_t set_step(erpp_plan *p, int64_t n, hipStream_t st);

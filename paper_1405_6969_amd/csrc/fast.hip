@@ -33,10 +33,6 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t grid) {
     return (b % kXcds) * (grid / kXcds) + b / kXcds;
 }
 
-__device__ __forceinline__ int64_t cell_key(const DevBox &B, int b0, int b1, int b2) {
-    return ((int64_t)b2 * B.n[1] + b1) * B.n[0] + b0;
-}
-
 // Sort key of the step's binning: cell row (b1, b2), then x-block of
 // 2^kXBlockShift cells.  Records of a cell row stay contiguous (the scatter's
 // ranges) and in x-block order (the gather's locality), while the counters are
@@ -1053,32 +1049,40 @@ __global__ void __launch_bounds__(kBlock) k_gather(const DevBox *__restrict__ Bs
 }
 
 // ------------------------------------------------------------- erpp_bin ----
-__global__ void __launch_bounds__(kBlock) k_bin_pos_count(const DevBox *__restrict__ Bs, int ibox,
+// Exact cell binning of any position array of one box; the geometry comes by
+// value, the histogram and the ranks through pointers (plan scratch, or the
+// static scratch of the allocation-free variant).
+__global__ void __launch_bounds__(kBlock) k_bin_pos_count(BinGeom G,
                                                           const double *__restrict__ pos,
                                                           int32_t *__restrict__ key,
                                                           int32_t *__restrict__ count,
                                                           int32_t *__restrict__ rank) {
-    const DevBox &B = Bs[ibox];
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= B.np) return;
-    const int64_t np = B.np;
+    if (p >= G.np) return;
+    const int64_t np = G.np;
     int b[3];
     double ph;
-    for (int d = 0; d < 3; ++d) cell_of(pos[d * np + p], B.L[d], B.dx[d], B.n[d], b[d], ph);
-    const int64_t k = cell_key(B, b[0], b[1], b[2]);
+    for (int d = 0; d < 3; ++d) cell_of(pos[d * np + p], G.L[d], G.dx[d], G.n[d], b[d], ph);
+    const int64_t k = ((int64_t)b[2] * G.n[1] + b[1]) * G.n[0] + b[0];
     key[p] = (int32_t)k;
-    rank[B.poff + p] = atomicAdd(&count[B.cell_off + k], 1);
+    rank[p] = atomicAdd(&count[k], 1);
 }
 
-__global__ void __launch_bounds__(kBlock) k_bin_pos_place(const DevBox *__restrict__ Bs, int ibox,
+__global__ void __launch_bounds__(kBlock) k_bin_pos_place(BinGeom G,
                                                           const int32_t *__restrict__ key,
                                                           const int32_t *__restrict__ start,
                                                           const int32_t *__restrict__ rank,
                                                           int32_t *__restrict__ perm) {
-    const DevBox &B = Bs[ibox];
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= B.np) return;
-    perm[start[key[p]] + rank[B.poff + p]] = (int32_t)p;
+    if (p >= G.np) return;
+    perm[start[key[p]] + rank[p]] = (int32_t)p;
+}
+
+// words[0..n) = 0 (a kernel rather than a memset node, so that a captured graph
+// replays it faithfully)
+__global__ void __launch_bounds__(kBlock) k_fill_zero(int32_t *__restrict__ words, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) words[i] = 0;
 }
 
 }  // namespace
@@ -1205,22 +1209,41 @@ hipError_t fast_gather(erpp_plan *P, double *u_p, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t bin_positions(const BinGeom &G, const double *pos, int32_t *key, int32_t *perm,
+                         int32_t *bin_start, int32_t *count, int32_t *rank, int32_t *part,
+                         int32_t *ticket, bool clear, hipStream_t st) {
+    const int64_t nc = (int64_t)G.n[0] * G.n[1] * G.n[2];
+    const unsigned blocks = (unsigned)((G.np + kBlock - 1) / kBlock);
+    if (clear) {
+        hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((nc + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, st, count, nc);
+        hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(kBlock), 0, st, ticket, (int64_t)1);
+    }
+    if (G.np > 0)
+        hipLaunchKernelGGL(k_bin_pos_count, dim3(blocks), dim3(kBlock), 0, st, G, pos, key, count,
+                           rank);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = scan_counts(count, nc, bin_start, part, ticket, nullptr, st);
+    if (e != hipSuccess) return e;
+    if (G.np > 0)
+        hipLaunchKernelGGL(k_bin_pos_place, dim3(blocks), dim3(kBlock), 0, st, G, key, bin_start,
+                           rank, perm);
+    return hipGetLastError();
+}
+
 hipError_t fast_bin_positions(erpp_plan *P, int ibox, const double *pos, int32_t *key,
                               int32_t *perm, int32_t *bin_start, hipStream_t st) {
     const DevBox &H = P->hbox[ibox];
-    const int64_t nc = (int64_t)H.n[0] * H.n[1] * H.n[2];
-    const unsigned blocks = (unsigned)((H.np + kBlock - 1) / kBlock);
-    if (H.np > 0)
-        hipLaunchKernelGGL(k_bin_pos_count, dim3(blocks), dim3(kBlock), 0, st, P->dbox, ibox, pos,
-                           key, P->s.count, P->s.rank);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    e = scan_counts(P->s.count + H.cell_off, nc, bin_start, P->s.part, P->s.ticket, nullptr, st);
-    if (e != hipSuccess) return e;
-    if (H.np > 0)
-        hipLaunchKernelGGL(k_bin_pos_place, dim3(blocks), dim3(kBlock), 0, st, P->dbox, ibox, key,
-                           bin_start, P->s.rank, perm);
-    return hipGetLastError();
+    BinGeom G;
+    for (int d = 0; d < 3; ++d) {
+        G.n[d] = H.n[d];
+        G.L[d] = H.L[d];
+        G.dx[d] = H.dx[d];
+    }
+    G.np = H.np;
+    return bin_positions(G, pos, key, perm, bin_start, P->s.count + H.cell_off,
+                         P->s.rank + H.poff, P->s.part, P->s.ticket, false, st);
 }
 
 }  // namespace erpp

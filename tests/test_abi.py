@@ -155,3 +155,26 @@ def test_setters_reject_a_null_plan():
     assert lib.erpp_plan_set_integrator(None, 0) == erpp.ERPP_EINVAL
     assert lib.erpp_plan_set_added_mass(None, 0, C.c_double(0.1), None) == erpp.ERPP_EINVAL
     assert lib.erpp_last_error()
+
+
+def test_bin_static_rejects_sizes_beyond_its_scratch():
+    """erpp_bin_static validates before touching the device: more cells or
+    particles than its static scratch holds, bad geometry and NULL outputs give
+    ERPP_EINVAL with a message."""
+    erpp, lib = _lib()
+    n = (C.c_int32 * 3)
+    L = (C.c_double * 3)(1.0, 1.0, 1.0)
+    fake = C.c_void_p(0x1000)
+    st = lib.erpp_bin_static(n(256, 128, 128), L, 10, fake, fake, fake, fake, None)
+    assert st == -1 and b"static scratch" in lib.erpp_last_error()
+    st = lib.erpp_bin_static(n(8, 8, 8), L, (1 << 21) + 1, fake, fake, fake, fake, None)
+    assert st == -1 and b"static scratch" in lib.erpp_last_error()
+    st = lib.erpp_bin_static(n(8, 0, 8), L, 10, fake, fake, fake, fake, None)
+    assert st == -1
+    st = lib.erpp_bin_static(n(8, 8, 8), (C.c_double * 3)(1.0, -1.0, 1.0), 10, fake, fake,
+                             fake, fake, None)
+    assert st == -1
+    st = lib.erpp_bin_static(n(8, 8, 8), L, 10, fake, fake, fake, None, None)
+    assert st == -1
+    st = lib.erpp_bin_static(n(8, 8, 8), L, 10, None, fake, fake, fake, None)
+    assert st == -1
