@@ -37,7 +37,7 @@ class Params(C.Structure):
                 ("sigma", C.c_double), ("cutoff", C.c_double), ("shear", C.c_double),
                 ("M", C.c_int32), ("dt", C.c_double), ("self_correction", C.c_int32),
                 ("g", C.c_double * 3), ("integrator", C.c_int32), ("a_p", C.c_double),
-                ("a_am", C.c_double)]
+                ("a_am", C.c_double), ("a_b", C.c_double)]
 
 
 _lib = None
@@ -58,7 +58,8 @@ def _load():
         lib.oracle_normalisation.argtypes = [P, d, d]
         lib.oracle_self_disturbance.argtypes = [P, d, d, d, d]
         lib.oracle_gather.argtypes = [P, d, d, d]
-        lib.oracle_step.argtypes = [P, C.c_int64, d, d, d, f32, d, d, i32, i32, d, d, d, i32]
+        lib.oracle_step.argtypes = [P, C.c_int64, d, d, d, f32, d, d, i32, i32, d, d, d, i32,
+                                    d, i32]
         lib.oracle_self_gradient.argtypes = [P, d, d, d, d]
         lib.oracle_grid_gradient.argtypes = [P, d, d, d]
         lib.oracle_self_laplacian.argtypes = [P, d, d, d, d]
@@ -82,7 +83,7 @@ def _f64(a):
 
 def make_params(n, L, np_, m_p, rho_f, nu, sigma, cutoff=3.0, shear=0.0, M=1,
                 dt=1e-3, self_correction=1, g=(0.0, 0.0, 0.0), integrator=0,
-                a_p=0.0, a_am=0.0) -> Params:
+                a_p=0.0, a_am=0.0, a_b=0.0) -> Params:
     P = Params()
     P.n = (C.c_int32 * 3)(*[int(v) for v in n])
     P.L = (C.c_double * 3)(*[float(v) for v in L])
@@ -94,9 +95,10 @@ def make_params(n, L, np_, m_p, rho_f, nu, sigma, cutoff=3.0, shear=0.0, M=1,
     P.integrator = int(integrator)
     P.a_p = float(a_p)
     P.a_am = float(a_am)
-    if P.a_am > 0.0 and (P.integrator != 0 or P.shear != 0.0):
-        raise ValueError("added mass is defined for the explicit Euler integrator in a "
-                         "box without mean shear")
+    P.a_b = float(a_b)
+    if (P.a_am > 0.0 or P.a_b > 0.0) and (P.integrator != 0 or P.shear != 0.0):
+        raise ValueError("the added-mass and Basset terms are defined for the explicit Euler "
+                         "integrator in a box without mean shear")
     for d in range(3):
         dxd = P.L[d] / P.n[d]
         R = int(np.ceil(P.cutoff * P.sigma / dxd))
@@ -240,6 +242,9 @@ class Run:
         # added-mass history: u~ and u~ + (a^2/10) lap u~ of the previous step
         self.am_hist = np.zeros((6, np_))
         self.am_valid = np.zeros(1, np.int32)
+        # Basset history: u~ + (a_b^2/6) lap u~ - v of the previous step
+        self.bs_hist = np.zeros((3, np_))
+        self.bs_valid = np.zeros(1, np.int32)
         self.n = 0
 
     def step(self, want_f=True, lo=None, wn=None):
@@ -254,6 +259,7 @@ class Run:
                             _ptr(self.tau, C.c_float), _ptr(self.ring_x, C.c_double),
                             _ptr(self.ring_d, C.c_double), _ptr(lo_a, C.c_int32),
                             _ptr(wn_a, C.c_int32), fp, _ptr(D, C.c_double),
-                            _ptr(self.am_hist, C.c_double), _ptr(self.am_valid, C.c_int32))
+                            _ptr(self.am_hist, C.c_double), _ptr(self.am_valid, C.c_int32),
+                            _ptr(self.bs_hist, C.c_double), _ptr(self.bs_valid, C.c_int32))
         self.n += 1
         return f, D

@@ -23,7 +23,11 @@
  *     eq. disturbance_velo];
  *   - the Stokes drag D = m_p (u~ - v) / tau_p and explicit Euler motion
  *     [Sec. 2.5, eqs. particle_motion and force_stokes_drag; Sec. 3.2,
- *     eq. Drag_one_way with tau_p].
+ *     eq. Drag_one_way with tau_p];
+ *   - optionally the other lines of the general force [Sec. 2.5,
+ *     eq. force_particle]: the Faxen terms, the added mass and the Basset
+ *     term, whose memory integral covers the last step only (Sec. 2.5, closing
+ *     paragraph), each with the self-disturbance removed.
  *
  * Readings where the paper leaves a choice (they are the same on the GPU):
  *   - sigma_R is given directly (a multiple of the grid spacing) and the delay
@@ -515,7 +519,8 @@ void oracle_gather(const oracle_params *P, const double *u, const double *x,
 void oracle_step(const oracle_params *P, int64_t n, const double *u,
                  double *x, double *v, const float *tau, double *ring_x,
                  double *ring_d, const int32_t lo[3], const int32_t wn[3],
-                 double *f, double *dout, double *am_hist, int32_t *am_valid)
+                 double *f, double *dout, double *am_hist, int32_t *am_valid,
+                 double *bs_hist, int32_t *bs_valid)
 {
     const int64_t np = P->np;
     const int32_t M = P->M;
@@ -530,6 +535,18 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
     const int am = P->a_am > 0.0;
     const double m_f = am ? P->rho_f * 4.0 / 3.0 * ORACLE_PI * P->a_am * P->a_am * P->a_am : 0.0;
     const double fam = P->a_am * P->a_am / 10.0;
+    /* Basset term (eq. force_particle, third line): in the two-way coupled
+       scheme the field carries the particle's earlier vorticity, so the memory
+       integral covers the last step only (closing paragraph of Sec. 2.5).  With
+       the bracket w = u~ + (a_b^2/6) lap u~ - v changing at the constant rate
+       (w^n - w^{n-1})/dt over that step,
+         6 pi mu a_b^2 int_{t-dt}^{t} [pi nu (t - s)]^{-1/2} ds (w^n - w^{n-1})/dt
+         = 12 pi mu a_b^2 (w^n - w^{n-1}) / sqrt(pi nu dt). */
+    const int bs = P->a_b > 0.0;
+    const double fbs = P->a_b * P->a_b / 6.0;
+    const double kbs = bs ? 12.0 * ORACLE_PI * P->rho_f * P->nu * P->a_b * P->a_b /
+                                sqrt(ORACLE_PI * P->nu * P->dt)
+                          : 0.0;
     int64_t p;
 
     /* 1. forcing from the drag delayed by eps_R = M dt */
@@ -546,12 +563,12 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
     if (P->self_correction && n >= M + 1) {
         int64_t slot = (n - 1 - M) % (M + 1);
         oracle_self_disturbance(P, x, ring_x + slot * lvl, ring_d + slot * lvl, vs);
-        if (fax != 0.0 || am)
+        if (fax != 0.0 || am || bs)
             oracle_self_laplacian(P, x, ring_x + slot * lvl, ring_d + slot * lvl, ls);
     }
     /* Faxen correction of the drag (eq. force_particle, first line):
        (a_p^2/6) lap u~ with u~ = u - v_self */
-    if (fax != 0.0 || am) oracle_grid_laplacian(P, u, x, lu);
+    if (fax != 0.0 || am || bs) oracle_grid_laplacian(P, u, x, lu);
     /* added mass: the gradient of u~ = u - v_self for the convective part of
        the fluid acceleration */
     double *gu = NULL, *gs = NULL;
@@ -598,37 +615,44 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
             double D[3], xn[3];
             int d;
             int64_t k;
-            if (am) {
-                /* eq. force_particle, first two lines, explicit Euler with the
-                   particle's own acceleration moved to the left:
-                     (m_p + m_f/2) dv/dt = S + m_f Du~/Dt + (m_f/2) dq/dt + m_p g_b,
+            if (am || bs) {
+                /* eq. force_particle, explicit Euler with the particle's own
+                   acceleration in the added-mass term moved to the left:
+                     (m_p + m_f/2) dv/dt = S + m_f Du~/Dt + (m_f/2) dq/dt + B + m_p g_b,
                    S = m_p (u~ + (a_p^2/6) lap u~ - v) / tau_p,
                    q = u~ + (a_am^2/10) lap u~,
-                   d/dt along the path: (value^n - value^{n-1}) / dt (zero on the
-                   first step, which has no previous value),
+                   B = kbs (w^n - w^{n-1}),  w = u~ + (a_b^2/6) lap u~ - v,
+                   d/dt along the path: (value^n - value^{n-1}) / dt, and B, zero on
+                   the first step that has no previous value;
                    Du~/Dt = du~/dt + (u~ - v) . grad u~ (material derivative from
                    the path derivative).  D = m_p dv/dt - m_p g_b is the
-                   hydrodynamic force handed to the fluid. */
-                double ut[3], q[3], S[3], Dm[3], acc[3];
-                const int valid = *am_valid;
+                   hydrodynamic force handed to the fluid.  Without added mass
+                   m_f = 0 and the scheme is explicit Euler with S + B. */
+                double ut[3], q[3], S[3], w[3], Dm[3], acc[3];
+                const int valid = am ? *am_valid : 0;
+                const int bvalid = bs ? *bs_valid : 0;
                 for (d = 0; d < 3; ++d) {
                     ut[d] = up[d * np + p] - vs[d * np + p];
                     q[d] = ut[d] + fam * (lu[d * np + p] - ls[d * np + p]);
                     S[d] = P->m_p * (ut[d] + fax * (lu[d * np + p] - ls[d * np + p]) -
                                      v[d * np + p]) / t;
+                    w[d] = ut[d] + fbs * (lu[d * np + p] - ls[d * np + p]) - v[d * np + p];
                 }
                 for (d = 0; d < 3; ++d) {
-                    double conv = 0.0;
+                    double conv = 0.0, dut = 0.0, dq = 0.0, Bs = 0.0;
                     int jd;
-                    for (jd = 0; jd < 3; ++jd)
-                        conv += (ut[jd] - v[jd * np + p]) *
-                                (gu[(3 * d + jd) * np + p] - gs[(3 * d + jd) * np + p]);
-                    double dut = valid ? (ut[d] - am_hist[d * np + p]) / P->dt : 0.0;
-                    double dq = valid ? (q[d] - am_hist[(3 + d) * np + p]) / P->dt : 0.0;
+                    if (am) {
+                        for (jd = 0; jd < 3; ++jd)
+                            conv += (ut[jd] - v[jd * np + p]) *
+                                    (gu[(3 * d + jd) * np + p] - gs[(3 * d + jd) * np + p]);
+                        dut = valid ? (ut[d] - am_hist[d * np + p]) / P->dt : 0.0;
+                        dq = valid ? (q[d] - am_hist[(3 + d) * np + p]) / P->dt : 0.0;
+                    }
+                    if (bvalid) Bs = kbs * (w[d] - bs_hist[d * np + p]);
                     Dm[d] = dut + conv;
-                    acc[d] = (S[d] + m_f * Dm[d] + 0.5 * m_f * dq + P->m_p * P->g[d]) /
+                    acc[d] = (S[d] + m_f * Dm[d] + 0.5 * m_f * dq + Bs + P->m_p * P->g[d]) /
                              (P->m_p + 0.5 * m_f);
-                    D[d] = S[d] + m_f * Dm[d] + 0.5 * m_f * (dq - acc[d]);
+                    D[d] = S[d] + m_f * Dm[d] + 0.5 * m_f * (dq - acc[d]) + Bs;
                 }
                 for (d = 0; d < 3; ++d) {
                     hx[d * np + p] = x[d * np + p];
@@ -636,8 +660,11 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
                     if (dout) dout[d * np + p] = D[d];
                     xn[d] = x[d * np + p] + P->dt * v[d * np + p];
                     v[d * np + p] += P->dt * acc[d];
-                    am_hist[d * np + p] = ut[d];
-                    am_hist[(3 + d) * np + p] = q[d];
+                    if (am) {
+                        am_hist[d * np + p] = ut[d];
+                        am_hist[(3 + d) * np + p] = q[d];
+                    }
+                    if (bs) bs_hist[d * np + p] = w[d];
                 }
             } else if (P->integrator == 0) {
                 for (d = 0; d < 3; ++d) {
@@ -712,6 +739,7 @@ void oracle_step(const oracle_params *P, int64_t n, const double *u,
         }
     }
     if (am) *am_valid = 1;
+    if (bs) *bs_valid = 1;
     free(gu);
     free(gs);
     free(vs);

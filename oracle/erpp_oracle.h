@@ -42,6 +42,8 @@ typedef struct {
     double  a_p;         /* particle radius of the Faxen term (a_p^2/6) lap u~; 0 = off */
     double  a_am;        /* particle radius of the added-mass terms (displaced mass
                             m_f = rho_f 4/3 pi a_am^3, Faxen part a_am^2/10); 0 = off */
+    double  a_b;         /* particle radius of the Basset term (coefficient 6 pi mu a_b^2,
+                            Faxen part a_b^2/6); 0 = off */
 } oracle_params;
 
 /* Cell key of each position and a stable counting sort by key.
@@ -90,12 +92,14 @@ void oracle_gather(const oracle_params *P, const double *u, const double *x,
  * ring slot n mod (M+1), and x^n, v^n -> x^{n+1}, v^{n+1} in place.
  * dout (optional, [3][np]) receives D^n.  With a_am > 0, am_hist ([6][np]:
  * u~ and u~ + (a_am^2/10) lap u~ of the previous step) and *am_valid (0 before
- * the first step with added mass) carry the added-mass history; otherwise both
- * may be NULL. */
+ * the first step with added mass) carry the added-mass history; with a_b > 0,
+ * bs_hist ([3][np]: u~ + (a_b^2/6) lap u~ - v of the previous step) and
+ * *bs_valid the Basset history; otherwise they may be NULL. */
 void oracle_step(const oracle_params *P, int64_t n, const double *u,
                  double *x, double *v, const float *tau, double *ring_x,
                  double *ring_d, const int32_t lo[3], const int32_t wn[3],
-                 double *f, double *dout, double *am_hist, int32_t *am_valid);
+                 double *f, double *dout, double *am_hist, int32_t *am_valid,
+                 double *bs_hist, int32_t *bs_valid);
 
 #ifdef __cplusplus
 }
