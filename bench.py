@@ -403,18 +403,20 @@ def bench_variants(box, w, tile, K, erpp, torch):
     mean shear (Heun and the added mass are defined for boxes at rest): the
     coupling step per graph replay and the update stage alone (HIP events), for
     explicit Euler, the exponential integrator, Heun with the self term removed
-    at each stage, the Faxen term (a_p = 0.6 dx) and the added mass on top of it
-    (a = 0.6 dx).  Units: ms per step, us for the update stage."""
+    at each stage, the Faxen term (a_p = 0.6 dx), the added mass on top of it
+    (a = 0.6 dx), the Basset term on top of the Faxen term, and all three
+    (the full force).  Units: ms per step, us for the update stage."""
     M, dt, s = w.M, w.dt, box.spec
     v = box.v.copy()
     if s.shear != 0.0:
         v[0] -= s.shear * (box.x[1] - 0.5 * box.L[1])
     a_p = 0.6 * box.dx[0]
-    cases = [("euler", None, 0.0, 0.0), ("exponential", erpp.EXPONENTIAL, 0.0, 0.0),
-             ("heun", erpp.HEUN, 0.0, 0.0), ("faxen", None, a_p, 0.0),
-             ("added_mass", None, a_p, a_p)]
+    cases = [("euler", None, 0.0, 0.0, 0.0), ("exponential", erpp.EXPONENTIAL, 0.0, 0.0, 0.0),
+             ("heun", erpp.HEUN, 0.0, 0.0, 0.0), ("faxen", None, a_p, 0.0, 0.0),
+             ("added_mass", None, a_p, a_p, 0.0), ("basset", None, a_p, 0.0, a_p),
+             ("full_force", None, a_p, a_p, a_p)]
     out = {"workload": f"{w.name} without mean shear", "steps": K, "a_p": round(a_p, 6)}
-    for name, integ, fax, am in cases:
+    for name, integ, fax, am, bs in cases:
         db = erpp.device_box(box.n, box.L, box.x, v, box.tau, box.u.astype(np.float32), M,
                              box.m_p, s.rho_f, s.nu, box.sigma, s.cutoff, 0.0,
                              precision=erpp.F32_FAST)
@@ -426,6 +428,8 @@ def bench_variants(box, w, tile, K, erpp, torch):
             plan.set_faxen(0, fax)
         if am > 0.0:
             plan.set_added_mass(0, am)
+        if bs > 0.0:
+            plan.set_basset(0, bs)
         warm = M + 4
         plan.run(0, warm, graph=True)
         torch.cuda.synchronize()

@@ -153,8 +153,8 @@ erpp_status erpp_plan_set_body_force(erpp_plan *plan, int32_t ibox, const double
  * (0, the default, turns it off).  lap u~ = the trilinear interpolation of the
  * 7-point nodal Laplacian of the carrier minus the Laplacian of the closed-form
  * self-disturbance (the projected Gaussian's second derivatives).  The added
- * mass is set by erpp_plan_set_added_mass; the Basset history force is not
- * provided.  Synchronises the device and invalidates captured graphs.
+ * mass is set by erpp_plan_set_added_mass, the Basset history force by
+ * erpp_plan_set_basset.  Synchronises the device and invalidates captured graphs.
  * ERPP_EINVAL for a bad plan, index or radius. */
 erpp_status erpp_plan_set_faxen(erpp_plan *plan, int32_t ibox, double a_p);
 
@@ -179,13 +179,34 @@ erpp_status erpp_plan_set_faxen(erpp_plan *plan, int32_t ibox, double a_p);
  * integrator or a sheared box. */
 erpp_status erpp_plan_set_added_mass(erpp_plan *plan, int32_t ibox, double a, double *hist);
 
+/* Basset history force of box `ibox` (eq. force_particle, third line) for
+ * particles of radius a (0, the default, turns it off).  The coupled field
+ * already carries the vorticity the particle produced before the current step,
+ * so the memory integral covers the last step only (Sec. 2.5, closing
+ * paragraph); with the bracket w = u~ + (a^2/6) lap u~ - v changing at the
+ * rate (w^n - w^{n-1})/dt over that step,
+ *   B^n = 6 pi mu a^2 int_{t-dt}^{t} [pi nu (t - s)]^{-1/2} ds (w^n - w^{n-1})/dt
+ *       = 12 pi mu a^2 (w^n - w^{n-1}) / sqrt(pi nu dt),
+ * mu = rho_f nu of the box, u~ and lap u~ as for the Faxen and added-mass
+ * terms (self-disturbance of the last injection removed).  Explicit Euler:
+ *   (m_p + m_f/2) (v^{n+1} - v^n)/dt = S + [added-mass terms] + B^n + m_p g_b
+ * (m_f = 0 without added mass), and the fluid receives the hydrodynamic force
+ * D = S + [added-mass terms] + B^n = m_p (v^{n+1} - v^n)/dt - m_p g_b.
+ * B = 0 on the first step after this call (no previous w).  hist: device,
+ * [3][np] FP64, caller-owned and left allocated while the term is on: w of the
+ * last step, written by every update (its contents on entry are not read).
+ * Explicit Euler only, boxes without mean shear only.  Synchronises the device
+ * and invalidates captured graphs.  ERPP_EINVAL for a bad plan, index, radius,
+ * nu or a NULL hist; ERPP_EUNSUPPORTED for another integrator or a sheared box. */
+erpp_status erpp_plan_set_basset(erpp_plan *plan, int32_t ibox, double a, double *hist);
+
 /* Particle integrator of every box (default ERPP_EULER).  The self-disturbance
  * removed from u~ is the same App. E closed form for all three (the fluid
  * receives one forcing step of the handed-over drag in each; Heun removes it at
  * each stage's position).  Applies to later steps; invalidates captured graphs.
  * Synchronises the device.  ERPP_EINVAL for a bad plan or kind;
  * ERPP_EUNSUPPORTED for Heun while a box has a mean shear, or for another
- * integrator than Euler while a box has the added-mass terms on. */
+ * integrator than Euler while a box has the added-mass or Basset terms on. */
 erpp_status erpp_plan_set_integrator(erpp_plan *plan, erpp_integrator kind);
 
 /* Autotuner (ERPP_F32_FAST): times every candidate pencil shape on the plan's own

@@ -24,7 +24,7 @@ EXPORTS = ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile", "erpp
            "erpp_stage_times", "erpp_plan_destroy", "erpp_status_string", "erpp_last_error",
            "erpp_fluid_create", "erpp_fluid_step", "erpp_fluid_destroy", "erpp_run_coupled",
            "erpp_plan_set_body_force", "erpp_plan_set_integrator", "erpp_plan_set_faxen",
-           "erpp_plan_set_added_mass", "erpp_bin_static"]
+           "erpp_plan_set_added_mass", "erpp_bin_static", "erpp_plan_set_basset"]
 
 
 class ErppError(RuntimeError):
@@ -84,12 +84,13 @@ def load(path: str = LIB_PATH):
     lib.erpp_plan_set_faxen.argtypes = [vp, i32, d]
     lib.erpp_plan_set_added_mass.argtypes = [vp, i32, d, vp]
     lib.erpp_bin_static.argtypes = [C.POINTER(i32), C.POINTER(d), i64, vp, vp, vp, vp, vp]
+    lib.erpp_plan_set_basset.argtypes = [vp, i32, d, vp]
     for name in ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile",
                  "erpp_plan_tune", "erpp_plan_bins", "erpp_bin", "erpp_scatter", "erpp_gather",
                  "erpp_step", "erpp_run", "erpp_stage_times", "erpp_fluid_create",
                  "erpp_fluid_step", "erpp_run_coupled", "erpp_plan_set_body_force",
                  "erpp_plan_set_integrator", "erpp_plan_set_faxen", "erpp_plan_set_added_mass",
-                 "erpp_bin_static"]:
+                 "erpp_bin_static", "erpp_plan_set_basset"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -252,6 +253,22 @@ class Plan:
                "erpp_plan_set_added_mass")
         self._am_hist = getattr(self, "_am_hist", {})
         self._am_hist[int(ibox)] = hist if a > 0.0 else None
+
+    def set_basset(self, ibox: int, a: float, hist=None):
+        """Basset term of box ibox for particles of radius a (0 turns it off), its
+        memory integral over the last step.  hist: FP64 device tensor [3, np]
+        (allocated here when None), kept by the plan while the term is on; it
+        holds u~ + (a^2/6) lap u~ - v of the last step."""
+        import torch
+        if a > 0.0 and hist is None:
+            np_ = self.boxes[ibox].x.shape[1]
+            hist = torch.zeros((3, np_), dtype=torch.float64, device=self.boxes[ibox].x.device)
+        if hist is not None and (hist.dtype != torch.float64 or not hist.is_contiguous()):
+            raise ValueError("hist must be a contiguous float64 tensor")
+        _check(self.lib.erpp_plan_set_basset(self.h, int(ibox), float(a), _ptr(hist)),
+               "erpp_plan_set_basset")
+        self._bs_hist = getattr(self, "_bs_hist", {})
+        self._bs_hist[int(ibox)] = hist if a > 0.0 else None
         return hist
 
     def set_integrator(self, kind: int):

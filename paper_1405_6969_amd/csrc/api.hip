@@ -50,10 +50,12 @@ using erpp::hip_fail;
 
 __global__ void k_set_step(int64_t *s, int64_t n) { *s = n; }
 
-// After an update with added mass: each such box now has a previous value.
+// After an update with the memory terms: each box using the added mass or the
+// Basset term now has a previous value of its path history.
 __global__ void k_am_mark(const erpp::DevBox *__restrict__ Bs, int nbox) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b < nbox && Bs[b].am_mf != 0.0) *Bs[b].am_valid = 1;
+    if (b < nbox && Bs[b].bs_k != 0.0) *Bs[b].bs_valid = 1;
 }
 __global__ void k_advance_step(int64_t *s) { *s += 1; }
 
@@ -175,7 +177,7 @@ hipError_t set_step(erpp_plan *p, int64_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t mark_added_mass(erpp_plan *p, hipStream_t st) {
+hipError_t mark_memory_terms(erpp_plan *p, hipStream_t st) {
     hipLaunchKernelGGL(k_am_mark, dim3((unsigned)((p->nbox + 63) / 64)), dim3(64), 0, st, p->dbox,
                        p->nbox);
     return hipGetLastError();
@@ -403,7 +405,7 @@ erpp_status erpp_plan_create(erpp_plan **out, const erpp_box *boxes, int32_t nbo
     }
     bool ok = alloc(&p->dbox, (size_t)nbox) == hipSuccess && alloc(&p->s.step, 2) == hipSuccess &&
               alloc(&p->s.rank, (size_t)np_total) == hipSuccess &&
-              alloc(&p->s.am_valid, (size_t)nbox) == hipSuccess;
+              alloc(&p->s.am_valid, 2 * (size_t)nbox) == hipSuccess;
     if (ok && prec == ERPP_F32_FAST)
         ok = alloc(&p->s.rec, 2 * (size_t)np_total) == hipSuccess &&
              alloc(&p->s.bsum, (size_t)std::max<int64_t>(p->nkey_total, 1)) == hipSuccess &&
@@ -421,10 +423,13 @@ erpp_status erpp_plan_create(erpp_plan **out, const erpp_box *boxes, int32_t nbo
         (void)hipGetLastError();
         return fail(ERPP_ENOMEM, "plan scratch for %lld particles", (long long)np_total);
     }
-    for (int b = 0; b < nbox; ++b) p->hbox[b].am_valid = p->s.am_valid + b;
+    for (int b = 0; b < nbox; ++b) {
+        p->hbox[b].am_valid = p->s.am_valid + b;
+        p->hbox[b].bs_valid = p->s.am_valid + nbox + b;
+    }
     erpp_status s = alloc_bins(p);
-    if (s == ERPP_OK && hipMemset(p->s.am_valid, 0, sizeof(int32_t) * nbox) != hipSuccess)
-        s = fail(ERPP_EHIP, "hipMemset of the added-mass flags");
+    if (s == ERPP_OK && hipMemset(p->s.am_valid, 0, 2 * sizeof(int32_t) * nbox) != hipSuccess)
+        s = fail(ERPP_EHIP, "hipMemset of the added-mass and Basset flags");
     if (s == ERPP_OK) s = upload_boxes(p);
     if (s == ERPP_OK && hipMemset(p->s.step, 0, 2 * sizeof(int64_t)) != hipSuccess)
         s = fail(ERPP_EHIP, "hipMemset of the step counter");
@@ -514,15 +519,46 @@ erpp_status erpp_plan_set_added_mass(erpp_plan *p, int32_t ibox, double a, doubl
     return ERPP_OK;
 }
 
+erpp_status erpp_plan_set_basset(erpp_plan *p, int32_t ibox, double a, double *hist) {
+    if (!p) return fail(ERPP_EINVAL, "plan is NULL");
+    if (ibox < 0 || ibox >= p->nbox) return fail(ERPP_EINVAL, "ibox %d out of range", ibox);
+    if (!std::isfinite(a) || a < 0.0) return fail(ERPP_EINVAL, "a must be finite and >= 0");
+    erpp::DevBox &B = p->hbox[ibox];
+    if (a > 0.0) {
+        if (!hist && B.np > 0) return fail(ERPP_EINVAL, "hist is NULL");
+        if (B.integ != 0)
+            return fail(ERPP_EUNSUPPORTED, "the Basset term runs with the explicit Euler "
+                                           "integrator only");
+        if (B.shear != 0.0)
+            return fail(ERPP_EUNSUPPORTED, "box %d: the Basset term needs shear = 0 (the path "
+                                           "difference would see the Lees-Edwards jump)", ibox);
+        const double nu = p->boxes[ibox].nu;
+        if (!(nu > 0.0))
+            return fail(ERPP_EINVAL, "box %d: the Basset term needs nu > 0", ibox);
+        erpp_status s = erpp::ensure_aux(p);
+        if (s != ERPP_OK) return s;
+    }
+    // 6 pi mu a^2 int_0^dt (pi nu s)^(-1/2) ds / dt = 12 pi mu a^2 / sqrt(pi nu dt)
+    const double nu = p->boxes[ibox].nu;
+    B.bs_k = a > 0.0 ? 12.0 * M_PI * B.rho_f * nu * a * a / std::sqrt(M_PI * nu * p->dt) : 0.0;
+    B.bs_fax = a * a / 6.0;
+    B.bs_hist = a > 0.0 ? hist : nullptr;
+    drop_graph(p);     // the update kernel's instance depends on it
+    HIP_OR_RETURN(hipDeviceSynchronize());
+    HIP_OR_RETURN(hipMemset(B.bs_valid, 0, sizeof(int32_t)));   // no previous value yet
+    HIP_OR_RETURN(hipMemcpy(p->dbox + ibox, &B, sizeof(erpp::DevBox), hipMemcpyHostToDevice));
+    return ERPP_OK;
+}
+
 erpp_status erpp_plan_set_integrator(erpp_plan *p, erpp_integrator kind) {
     if (!p) return fail(ERPP_EINVAL, "plan is NULL");
     if (kind != ERPP_EULER && kind != ERPP_EXPONENTIAL && kind != ERPP_HEUN)
         return fail(ERPP_EINVAL, "unknown integrator %d", (int)kind);
     if (kind != ERPP_EULER)
         for (int32_t b = 0; b < p->nbox; ++b)
-            if (p->hbox[b].am_mf != 0.0)
-                return fail(ERPP_EUNSUPPORTED, "box %d: the added-mass terms run with the "
-                                               "explicit Euler integrator only", b);
+            if (p->hbox[b].am_mf != 0.0 || p->hbox[b].bs_k != 0.0)
+                return fail(ERPP_EUNSUPPORTED, "box %d: the added-mass and Basset terms run "
+                                               "with the explicit Euler integrator only", b);
     if (kind == ERPP_HEUN)
         for (int32_t b = 0; b < p->nbox; ++b)
             if (p->boxes[b].shear != 0.0)

@@ -408,43 +408,55 @@ __device__ __forceinline__ void finish_particle(const DevBox &B, int64_t p, cons
     for (int d = 0; d < 3; ++d) B.v[d * np + p] = vn[d];
 }
 
-// Explicit Euler step with the added-mass terms (eq. force_particle, first two
-// lines), given u~ = u - v_self, lap u~ and grad u~ at x^n:
-//   (m_p + m_f/2) dv/dt = S + m_f Du~/Dt + (m_f/2) dq/dt + m_p g_b,
+// Explicit Euler step with the memory terms of eq. force_particle: the added
+// mass (second line) and the Basset term (third line), given u~ = u - v_self,
+// lap u~ and grad u~ at x^n:
+//   (m_p + m_f/2) dv/dt = S + m_f Du~/Dt + (m_f/2) dq/dt + B + m_p g_b,
 //   S = m_p (u~ + fax lap u~ - v) / tau_p,   q = u~ + am_fax lap u~,
 //   Du~/Dt = du~/dt + (u~ - v) . grad u~,
-// with d/dt the difference along the particle path over the last step (zero on
-// the first step after the terms were switched on).  The fluid receives the
-// hydrodynamic force D = m_p dv/dt - m_p g_b.  FP64.
-__device__ __forceinline__ void update_particle_am(const DevBox &B, int64_t p, double dt,
-                                                   const double xp[3], const double ut[3],
-                                                   const double lap[3], const double grad[9],
-                                                   int valid, double *hx, double *hdD,
-                                                   float *hdF) {
+//   B = bs_k (w^n - w^{n-1}),   w = u~ + bs_fax lap u~ - v
+// (the Basset memory integral over the last step only, with the bracket's
+// derivative the difference over that step), with d/dt the difference along the
+// particle path over the last step; each term is zero on the first step after
+// it was switched on, and absent (m_f = 0, bs_k = 0) when off.  The fluid
+// receives the hydrodynamic force D = m_p dv/dt - m_p g_b.  FP64.
+__device__ __forceinline__ void update_particle_mem(const DevBox &B, int64_t p, double dt,
+                                                    const double xp[3], const double ut[3],
+                                                    const double lap[3], const double grad[9],
+                                                    int am_valid, int bs_valid, double *hx,
+                                                    double *hdD, float *hdF) {
 #pragma clang fp contract(off)
     const int64_t np = B.np;
     const double t = (double)B.tau[p];
     const double mf = B.am_mf, mp = B.m_p;
-    double v[3], q[3], S[3], D[3], xn[3], vn[3];
+    const bool am = mf != 0.0, bs = B.bs_k != 0.0;
+    double v[3], q[3], S[3], w[3], D[3], xn[3], vn[3];
     for (int d = 0; d < 3; ++d) {
         v[d] = B.v[d * np + p];
         q[d] = ut[d] + B.am_fax * lap[d];
         S[d] = mp * (ut[d] + B.fax * lap[d] - v[d]) / t;
+        w[d] = ut[d] + B.bs_fax * lap[d] - v[d];
     }
     for (int d = 0; d < 3; ++d) {
-        double conv = 0.0;
-        for (int j = 0; j < 3; ++j) conv += (ut[j] - v[j]) * grad[3 * d + j];
-        const double dut = valid ? (ut[d] - B.am_hist[d * np + p]) / dt : 0.0;
-        const double dq = valid ? (q[d] - B.am_hist[(3 + d) * np + p]) / dt : 0.0;
+        double conv = 0.0, dut = 0.0, dq = 0.0, Bs = 0.0;
+        if (am) {
+            for (int j = 0; j < 3; ++j) conv += (ut[j] - v[j]) * grad[3 * d + j];
+            dut = am_valid ? (ut[d] - B.am_hist[d * np + p]) / dt : 0.0;
+            dq = am_valid ? (q[d] - B.am_hist[(3 + d) * np + p]) / dt : 0.0;
+        }
+        if (bs && bs_valid) Bs = B.bs_k * (w[d] - B.bs_hist[d * np + p]);
         const double Dm = dut + conv;
-        const double acc = (S[d] + mf * Dm + 0.5 * mf * dq + mp * B.gb[d]) / (mp + 0.5 * mf);
-        D[d] = S[d] + mf * Dm + 0.5 * mf * (dq - acc);
+        const double acc = (S[d] + mf * Dm + 0.5 * mf * dq + Bs + mp * B.gb[d]) / (mp + 0.5 * mf);
+        D[d] = S[d] + mf * Dm + 0.5 * mf * (dq - acc) + Bs;
         xn[d] = xp[d] + dt * v[d];
         vn[d] = v[d] + dt * acc;
     }
     for (int d = 0; d < 3; ++d) {
-        B.am_hist[d * np + p] = ut[d];
-        B.am_hist[(3 + d) * np + p] = q[d];
+        if (am) {
+            B.am_hist[d * np + p] = ut[d];
+            B.am_hist[(3 + d) * np + p] = q[d];
+        }
+        if (bs) B.bs_hist[d * np + p] = w[d];
     }
     finish_particle(B, p, xp, D, xn, vn, hx, hdD, hdF);
 }

@@ -52,6 +52,10 @@ struct DevBox {
     double am_fax;       // added mass: Faxen coefficient a^2 / 10 of its d/dt term
     double *am_hist;     // added mass: [6][np] u~ and u~ + am_fax lap u~ of the last step
     int32_t *am_valid;   // added mass: 0 until the first step with the terms has run
+    double bs_k;         // Basset: 12 pi mu a_b^2 / sqrt(pi nu dt) (0: no Basset term)
+    double bs_fax;       // Basset: Faxen coefficient a_b^2 / 6 of its bracket
+    double *bs_hist;     // Basset: [3][np] w = u~ + bs_fax lap u~ - v of the last step
+    int32_t *bs_valid;   // Basset: 0 until the first step with the term has run
     double s2s;          // sigma_s^2 = sigma^2 + 2 nu dt  (self-disturbance width)
     double pref;         // -(dt/rho_f) (2 pi sigma_s^2)^(-3/2)
     float dxf[3];
@@ -99,7 +103,8 @@ struct Scratch {
     double *pphi = nullptr;      // [3][np_total] offsets inside the base cell
     int32_t *pbase = nullptr;    // [3][np_total] base cell
     // both
-    int32_t *am_valid = nullptr; // [nbox]          added-mass history present (per box)
+    int32_t *am_valid = nullptr; // [2 nbox]        history present (per box): added mass,
+                                 //                 then Basset
     int64_t *step = nullptr;     // [2] step index: [0] next step to run (set by the host,
                                  // advanced by the scan of the fast path or by a kernel
                                  // of its own in the plain path), [1] the step in progress
@@ -169,7 +174,8 @@ hipError_t plain_scatter_stages(erpp_plan *p, hipStream_t st);
 hipError_t plain_update_stage(erpp_plan *p, hipStream_t st);
 hipError_t set_step(erpp_plan *p, int64_t n, hipStream_t st);
 hipError_t advance_step(erpp_plan *p, hipStream_t st);
-hipError_t mark_added_mass(erpp_plan *p, hipStream_t st);  // after an update: history present
+// after an update: the added-mass and Basset histories of the boxes using them exist
+hipError_t mark_memory_terms(erpp_plan *p, hipStream_t st);
 bool fill_box_tiles(erpp_plan *p);
 erpp_status ensure_aux(erpp_plan *p);   // allocate Scratch::aux / vrec (FP32 path)          // tiles, blocks, LDS layout; false if it does not fit
 // start = exclusive scan of count, count = 0; with stepp, also step[1] = step[0]++

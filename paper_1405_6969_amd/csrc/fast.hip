@@ -835,7 +835,7 @@ __global__ void __launch_bounds__(kBlock) k_gather_sorted(const DevBox *__restri
     trilinear<float>(B, (const float *)B.u, xp, u);
     const int64_t slot = B.poff + r;
     up[slot] = make_double4(u[0], u[1], u[2], 0.0);
-    const bool lap = LAP && (B.fax != 0.0 || B.am_mf != 0.0);
+    const bool lap = LAP && (B.fax != 0.0 || B.am_mf != 0.0 || B.bs_k != 0.0);
     const bool grad = GRAD && B.am_mf != 0.0;
     double l[3], g[9];
     if (lap && grad)
@@ -975,7 +975,7 @@ __global__ void __launch_bounds__(kBlock) k_update(const DevBox *__restrict__ Bs
     } else {
         trilinear<float>(B, (const float *)B.u, xp, up);
     }
-    const bool lpre = (FAX || AM) && rec && (B.fax != 0.0 || B.am_mf != 0.0);
+    const bool lpre = (FAX || AM) && rec && (B.fax != 0.0 || B.am_mf != 0.0 || B.bs_k != 0.0);
     double lu[3] = {0.0, 0.0, 0.0};
     if (lpre) {
         const double4 l = aux[sr];
@@ -984,22 +984,25 @@ __global__ void __launch_bounds__(kBlock) k_update(const DevBox *__restrict__ Bs
         lu[2] = l.z;
     }
     const int64_t sw = n % (M + 1);
-    if (AM && B.am_mf != 0.0) {
+    if (AM && (B.am_mf != 0.0 || B.bs_k != 0.0)) {
         double vs[3], ut[3], lap[3], grad[9];
         self_terms<false>(B, p, n, M, selfc, xp, up, vs, lu, false);
         for (int d = 0; d < 3; ++d) ut[d] = up[d] - vs[d];
         if (rec) {
+            // the gather wrote the gradient only for boxes with added mass, the
+            // only ones that use it
             for (int d = 0; d < 3; ++d) lap[d] = lu[d];
             for (int j = 0; j < 3; ++j) {
-                const double4 g = aux[(1 + j) * npt + sr];
+                const double4 g = B.am_mf != 0.0 ? aux[(1 + j) * npt + sr]
+                                                 : make_double4(0.0, 0.0, 0.0, 0.0);
                 grad[j] = g.x;
                 grad[3 + j] = g.y;
                 grad[6 + j] = g.z;
             }
         }
         am_terms(B, p, n, M, selfc, xp, lap, grad, rec);
-        update_particle_am(B, p, dt, xp, ut, lap, grad, *B.am_valid, B.ring_x + sw * 3 * np,
-                           nullptr, (float *)B.ring_d + sw * 3 * np);
+        update_particle_mem(B, p, dt, xp, ut, lap, grad, *B.am_valid, *B.bs_valid,
+                            B.ring_x + sw * 3 * np, nullptr, (float *)B.ring_d + sw * 3 * np);
         return;
     }
     double vs[3];
@@ -1162,10 +1165,11 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                 for (const auto &B : P->hbox) {
                     fax = fax || B.fax != 0.0;
                     heun = heun || B.integ == 2;
-                    am = am || B.am_mf != 0.0;
+                    am = am || B.am_mf != 0.0 || B.bs_k != 0.0;
                 }
                 const bool lap = fax || am;
-                // added mass runs with explicit Euler only (checked by the setters)
+                // the added-mass and Basset terms run with explicit Euler only (checked
+                // by the setters)
                 auto gat = am ? k_gather_sorted<true, true, false>
                          : lap ? (heun ? k_gather_sorted<true, false, true>
                                        : k_gather_sorted<true, false, false>)
@@ -1182,7 +1186,7 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                                    dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step + 1, P->M, P->dt, P->self_correction,
                                    P->s.up, P->s.sl, P->s.aux, P->np_total);
-                if (am) return mark_added_mass(P, st);
+                if (am) return mark_memory_terms(P, st);
             }
             break;
         default:

@@ -145,7 +145,7 @@ __device__ __forceinline__ void plain_terms(const DevBox &B, int64_t p, int64_t 
     }
 }
 
-// Added mass: u~ = u - v_self, lap u~ and grad u~ at pos, each the
+// Memory terms (added mass, Basset): u~ = u - v_self, lap u~ and grad u~ at pos, each the
 // interpolated carrier stencil minus the closed form of the self-disturbance of
 // the last injection (FP64).
 __device__ void plain_am_terms(const DevBox &B, int64_t p, int64_t n, int M, int selfc,
@@ -188,11 +188,11 @@ __global__ void __launch_bounds__(kBlock) k_plain_update(const DevBox *__restric
     const int64_t np = B.np;
     double xp[3] = {B.x[p], B.x[np + p], B.x[2 * np + p]};
     const int64_t sw = n % (M + 1);
-    if (B.am_mf != 0.0) {
+    if (B.am_mf != 0.0 || B.bs_k != 0.0) {
         double ut[3], lap[3], grad[9];
         plain_am_terms(B, p, n, M, selfc, xp, ut, lap, grad);
-        update_particle_am(B, p, dt, xp, ut, lap, grad, *B.am_valid, B.ring_x + sw * 3 * np,
-                           (double *)B.ring_d + sw * 3 * np, nullptr);
+        update_particle_mem(B, p, dt, xp, ut, lap, grad, *B.am_valid, *B.bs_valid,
+                            B.ring_x + sw * 3 * np, (double *)B.ring_d + sw * 3 * np, nullptr);
         return;
     }
     double up[3], vs[3];
@@ -241,7 +241,7 @@ hipError_t plain_stage(erpp_plan *P, int k, hipStream_t st) {
                 hipLaunchKernelGGL(k_plain_update, dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step, P->M, P->dt, P->self_correction);
                 for (const auto &B : P->hbox)
-                    if (B.am_mf != 0.0) return mark_added_mass(P, st);
+                    if (B.am_mf != 0.0 || B.bs_k != 0.0) return mark_memory_terms(P, st);
             }
             break;
         default:
