@@ -503,6 +503,18 @@ __global__ void __launch_bounds__(kBlock) k_pencil_scale(const DevBox *__restric
 
 // --------------------------------------------------------------- scatter ----
 
+// Rows of one work item of the scatter: a band of kBand consecutive stencil rows
+// dy of one plane dz (all lanes of a pass take the same band).
+constexpr int kBand = 3;
+
+// Fourth descriptor word of a raw (unformatted, unswizzled) gfx9 buffer resource.
+constexpr int kBufferWord3 = 0x00020000;
+
+// One 16-byte half of a record, at a byte offset from the record array.
+__device__ __forceinline__ float4 rec_load(__amdgpu_buffer_rsrc_t r, int byteoff) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, byteoff, 0, 0));
+}
+
 // Makes the four values available in registers at this point (the compiler
 // places the wait for their load here); emits no instruction.
 __device__ __forceinline__ void pin4(float4 &v) {
@@ -528,12 +540,16 @@ __device__ __forceinline__ uint32_t fixed32(float v) {
 // particles whose row lies on pencil plane z are those with b2 = o2 + z - dz and
 // b1 in [o1 - dy, o1 - dy + e1): since records are sorted by cell and a pencil
 // spans all of x, that is one contiguous record range (two when it wraps in y).
-// A wave takes a class and runs one lane per (particle, row) over the ranges of
-// all e2 planes, so its 64 lanes walk rows of the same relative offset, whose
-// lengths differ by at most a node or two, and no row is ever cut by the tile.
-// Records are read straight from the cell-sorted array (L2), one pass ahead of
-// use, so the loads overlap the previous pass's LDS atomics (they wait on a
-// different counter).
+// Classes are taken kBand rows at a time (consecutive dy of one dz): a wave
+// takes a band and runs one lane per (particle, band) over the ranges of all e2
+// planes, so its 64 lanes walk rows of the same relative offsets, whose lengths
+// differ by at most a node or two, no row is ever cut by the tile, and the
+// record load and decode of an item serve kBand rows.  Records are read straight
+// from the cell-sorted array (L2) through a buffer resource, one item ahead of
+// use, so the loads overlap the previous item's LDS atomics (they wait on a
+// different counter).  Per row, the weight of the first node is one exp2; the
+// ratio to the next node is the item's factor exp2(c hx^2 (2 phi_x - 1)) times a
+// tabulated power exp2(-2 c hx^2 m) of the first node's offset m.
 //
 // The LDS tile keeps each pencil row unwrapped in x: a row's nodes b0 + m,
 // m in [mlo, mhi], sit at index b0 + m - mlo of a row of Nx + (mhi - mlo) + 1
@@ -555,15 +571,17 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
                                                            const int32_t *__restrict__ start,
                                                            const float4 *__restrict__ rec,
                                                            const float *__restrict__ pscale,
-                                                           int64_t npen) {
+                                                           int64_t npen, int64_t npart) {
     extern __shared__ int32_t lds[];
-    __shared__ int s_cls[256];
+    __shared__ int s_cls[256];            // row bands: dz, first dy, rows
     __shared__ int s_ncls;
     __shared__ int s_next;                // next class to hand out
+    __shared__ float s_q[32];             // exp2(-2 c hx^2 m), m = mlo .. mhi in x
     // workgroups are dealt to the 8 XCDs round-robin; give each XCD (its own L2)
     // one contiguous run of pencils, whose record windows overlap
     const int64_t pen = xcd_block(blockIdx.x, gridDim.x);
     if (pen >= npen) return;
+    const int64_t n = *stepp;
     const int bi = box_of_block(Bs, nbox, pen, [](const DevBox &b) { return b.blk_t; });
     const DevBox &B = Bs[bi];
     const int t = (int)(pen - B.blk_t);
@@ -581,7 +599,6 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
     const int mlo1 = B.mlo[1], mhi1 = B.mhi[1];
     const int mlo2 = B.mlo[2], mhi2 = B.mhi[2];
     for (int i = tid; i < 3 * T2 * T1 * PXa; i += NT) acc[i] = 0;
-    const int64_t n = *stepp;
     float scale = 1.0f;
     if (n >= M) {
         const int WY = e1 + mhi1 - mlo1;      // window cell rows in y, z
@@ -604,12 +621,27 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
             s_ncls = 0;
             s_next = 0;
         }
+        if (tid <= mhi0 - mlo0)
+            s_q[tid] = exp2f(-2.0f * B.cexp * B.dxf[0] * B.dxf[0] * (float)(mlo0 + tid));
         __syncthreads();
-        if (tid < ny * nz) {
-            const int dy = mlo1 + tid % ny, dz = mlo2 + tid / ny;
-            const float ay = (float)(dy >= 1 ? dy - 1 : -dy) * B.dxf[1];
+        if (tid < nz) {
+            // the rows dy of plane dz that some particle reaches form one interval
+            // (the test is convex in |dy|); it is cut into bands of kBand rows
+            const int dz = mlo2 + tid;
             const float az = (float)(dz >= 1 ? dz - 1 : -dz) * B.dxf[2];
-            if (fmaf(ay, ay, az * az) <= cut) s_cls[atomicAdd(&s_ncls, 1)] = tid;
+            int lo = 1 << 20, hi = -(1 << 20);
+            for (int k = 0; k < ny; ++k) {
+                const int dy = mlo1 + k;
+                const float ay = (float)(dy >= 1 ? dy - 1 : -dy) * B.dxf[1];
+                if (fmaf(ay, ay, az * az) <= cut) {
+                    lo = min(lo, dy);
+                    hi = max(hi, dy);
+                }
+            }
+            for (int dy0 = lo; dy0 <= hi; dy0 += kBand) {
+                const int nb = min(kBand, hi - dy0 + 1);
+                s_cls[atomicAdd(&s_ncls, 1)] = (dz + 64) | ((dy0 + 64) << 8) | (nb << 16);
+            }
         }
         __syncthreads();
         // records of window plane wz, cell rows j in [ja, ja + len): [g0, g1) and,
@@ -629,10 +661,14 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
         };
         // fixed-point scale of the pencil (k_pencil_scale)
         scale = pscale[pen];
+        // the records through a buffer resource: 32-bit byte offsets
+        const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)rec, (short)0, (int)(32 * npart), kBufferWord3);
         const int64_t slot = (n - M) % (M + 1);
         float hx = B.dxf[0], hy = B.dxf[1], hz = B.dxf[2];
         float c = B.cexp;
         const float qx = exp2f(-2.0f * c * hx * hx);
+        const float chx2 = c * hx * hx;
         // box constants of the row loop, pinned in registers: reloading them from
         // the box descriptor inside the loop would wait on the LDS counter, i.e.
         // on the previous row's atomics
@@ -650,21 +686,25 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
             if (lane == 0) cn = atomicAdd(&s_next, 1);
             const int ci = __builtin_amdgcn_readfirstlane(cn);
             if (ci >= ncls) break;
-            const int cl = s_cls[ci];
-            const int dy = mlo1 + cl % ny, dz = mlo2 + cl / ny;
-            // lane k < 2 e2: part (k & 1) of the records of plane k >> 1.  Part 0
-            // holds cell rows b1 in [b1a, ...), part 1 (rows wrapped past Ny)
-            // b1 in [0, ...), with b1a = (o1 - dy) mod Ny: the pencil row of a
-            // record is lz T1 + b1 - b1a (+ Ny in part 1), so its LDS node index is
-            // b1 PXa + b0 + m + rowoff with rowoff uniform over the range
-            const int b1a = wrap_index(o1 - dy, Ny);
-            int len = 0, gb = 0, rowoff = 0;
+            const int clw = s_cls[ci];
+            const int dz = (clw & 255) - 64, dy0 = ((clw >> 8) & 255) - 64, nb = clw >> 16;
+            // rows dy0 .. dy0 + nb - 1 of plane dz.  The records whose band reaches the
+            // pencil: cell rows b1 in [o1 - dy0 - nb + 1, o1 - dy0 + e1), window rows
+            // ja .. ja + len - 1.  Lane k < 2 e2: part (k & 1) of the records of plane
+            // k >> 1; part 0 holds cell rows b1 in [b1a, ...), part 1 (wrapped past
+            // Ny) b1 in [0, ...).  A record's window row is b1 + jo (jo uniform over
+            // the range); its row dy0 + r lands on pencil row b1 + jo + r - nb + 1
+            // and LDS node index b1 PXa + b0 + m + rowoff + r PXa.
+            const int ja = mhi1 - dy0 - nb + 1, wlen = e1 + nb - 1;
+            const int b1a = wrap_index(o1 - dy0 - nb + 1, Ny);
+            int len = 0, gb = 0, rowoff = 0, jo = 0;
             if (lane < nr) {
                 int g0, g1, h0, h1;
-                ranges((lane >> 1) + mhi2 - dz, mhi1 - dy, e1, g0, g1, h0, h1);
+                ranges((lane >> 1) + mhi2 - dz, ja, wlen, g0, g1, h0, h1);
                 gb = (lane & 1) ? h0 : g0;
                 len = (lane & 1) ? h1 - h0 : g1 - g0;
-                rowoff = ((lane >> 1) * T1 - b1a + ((lane & 1) ? Ny : 0)) * PXa - mlo0;
+                jo = -b1a + ((lane & 1) ? Ny : 0);
+                rowoff = ((lane >> 1) * T1 + jo - nb + 1) * PXa - mlo0;
             }
             const int incl = wave_incl_scan(len);
             const int total = __shfl(incl, 63, 64);
@@ -673,62 +713,83 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
             const int pre = incl - len;
             const int off = gb - pre;
             constexpr int kMaxRanges = 2 * TZ;
-            int pre_k[kMaxRanges], off_k[kMaxRanges], row_k[kMaxRanges];
+            int pre_k[kMaxRanges], off_k[kMaxRanges], row_k[kMaxRanges], jo_k[kMaxRanges];
 #pragma unroll
             for (int k = 0; k < kMaxRanges; ++k) {
                 pre_k[k] = __builtin_amdgcn_readlane(pre, k);
                 off_k[k] = __builtin_amdgcn_readlane(off, k);
                 row_k[k] = __builtin_amdgcn_readlane(rowoff, k);
+                jo_k[k] = __builtin_amdgcn_readlane(jo, k);
             }
-            auto record_of = [&](int q, int &ro) -> int {
+            // byte offset of item q's record, and the LDS row offset and window-row
+            // offset of its range
+            auto record_of = [&](int q, int &ro, int &jr) -> int {
                 int o = off_k[0];
                 ro = row_k[0];
+                jr = jo_k[0];
 #pragma unroll
                 for (int k = 1; k < kMaxRanges; ++k)
                     if (k < nr && q >= pre_k[k]) {
                         o = off_k[k];
                         ro = row_k[k];
+                        jr = jo_k[k];
                     }
-                return q + o;
+                return (q + o) << 5;
             };
             // lane l takes the items [l P, l P + P): the lanes of one pass are spread
             // over the whole range, so fewer of them add into the same node or bank
             const int P = (total + 63) >> 6;
             int q = lane * P;
             const int qend = min(q + P, total);
-            // one stencil row: range, first weight, then the node walk
-            auto row = [&](const float4 qa, const float4 qb, const int ro) {
+            // one band of an item: per row the pencil test, the sphere test, the
+            // range, the first weight, then the node walk
+            const float tzc = (float)dz;
+            auto band = [&](const float4 qa, const float4 qb, const int ro, const int jr) {
                 const uint32_t ijk = __float_as_uint(qa.w);
                 const int b0 = (int)(ijk & 2047u);
                 const int b1 = (int)((ijk >> 11) & 2047u);
-                const float tyv = d1(dy, qa.y, hy);
-                const float tzv = d1(dz, qa.z, hz);
-                const float ryz = fmaf(tyv, tyv, tzv * tzv);
-                if (ryz > cutv) return;
-                int rlo, rhi;
-                row_range(qa.x, ryz, K, &B, slot, __float_as_int(qb.w), dy, dz, rlo, rhi);
-                if (rlo > rhi) return;
-                // raw v_exp_f32: both arguments lie in [-2 R^2 c, 0], far from underflow
-                const float t0 = ((float)rlo - qa.x) * hx;
-                float w = __builtin_amdgcn_exp2f(-fmaf(t0, t0, ryz) * c);
-                float rr = __builtin_amdgcn_exp2f(-c * hx * fmaf(2.0f, t0, hx));
-                // contributions a_c w of the row's first node, advanced along the row
-                // by the weight ratio rr (itself advanced by qx)
-                const float sw = scale * w;
-                float cx = qb.x * sw, cy = qb.y * sw, cz = qb.z * sw;
-                const int node = (int)__umul24((unsigned)b1, (unsigned)PXa) + b0 + rlo + ro;
-                uint32_t *ap = (uint32_t *)acc + 3 * node;
-                uint32_t *const ae = ap + 3 * (rhi - rlo + 1);
-                do {
-                    atomicAdd(ap, fixed32(cx));
-                    atomicAdd(ap + 1, fixed32(cy));
-                    atomicAdd(ap + 2, fixed32(cz));
-                    cx *= rr;
-                    cy *= rr;
-                    cz *= rr;
-                    rr *= qx;
-                    ap += 3;
-                } while (ap != ae);
+                const int rowx = (int)__umul24((unsigned)b1, (unsigned)PXa) + b0 + ro;
+                const int y0 = b1 + jr - nb + 1;          // pencil row of the band's first row
+                const float tzv = (tzc - qa.z) * hz;
+                const float tz2 = tzv * tzv;
+                // ratio w(m + 1) / w(m) along a row is exp2(c hx^2 (2 phi_x - 1)) times
+                // s_q[m - mlo] = exp2(-2 c hx^2 m); the amplitudes carry the scale
+                const float ra = __builtin_amdgcn_exp2f(chx2 * fmaf(2.0f, qa.x, -1.0f));
+                const float sax = qb.x * scale, say = qb.y * scale, saz = qb.z * scale;
+#pragma unroll
+                for (int r = 0; r < kBand; ++r) {
+                    if (r >= nb) break;
+                    const int y = y0 + r;
+                    if (y < 0 || y >= e1) continue;
+                    const int dy = dy0 + r;
+                    const float tyv = d1(dy, qa.y, hy);
+                    const float ryz = fmaf(tyv, tyv, tz2);
+                    if (ryz > cutv) continue;
+                    int rlo, rhi;
+                    row_range(qa.x, ryz, K, &B, slot, __float_as_int(qb.w), dy, dz, rlo, rhi);
+                    if (rlo > rhi) continue;
+                    // raw v_exp_f32: the argument lies in [-2 R^2 c, 0], far from underflow
+                    const float t0 = ((float)rlo - qa.x) * hx;
+                    const float w = __builtin_amdgcn_exp2f(-fmaf(t0, t0, ryz) * c);
+                    // weight ratio of the first step along the row: the item's factor
+                    // times the tabulated power of the first node
+                    float rr = ra * s_q[rlo - K.mlo0];
+                    // contributions a_c w of the row's first node, advanced along the row
+                    // by the weight ratio rr (itself advanced by qx)
+                    float cx = sax * w, cy = say * w, cz = saz * w;
+                    int a = 3 * (rowx + rlo + r * PXa);
+                    int cntn = rhi - rlo + 1;
+                    do {
+                        atomicAdd((uint32_t *)&lds[a], fixed32(cx));
+                        atomicAdd((uint32_t *)&lds[a + 1], fixed32(cy));
+                        atomicAdd((uint32_t *)&lds[a + 2], fixed32(cz));
+                        cx *= rr;
+                        cy *= rr;
+                        cz *= rr;
+                        rr *= qx;
+                        a += 3;
+                    } while (--cntn != 0);
+                }
             };
             // records are fetched one item ahead into two register sets used in
             // turn (no copies between them).  The fetch is unconditional (the last
@@ -736,30 +797,30 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
             // fetch is issued, so the wait for a set never waits for the younger
             // fetch behind it.
             float4 ra0, rb0, ra1, rb1;
-            int ro0 = 0, ro1 = 0;
+            int ro0 = 0, ro1 = 0, jr0 = 0, jr1 = 0;
             if (q < qend) {
-                const int g = record_of(q, ro0);
-                ra0 = rec[2 * (int64_t)g];
-                rb0 = rec[2 * (int64_t)g + 1];
+                const int g = record_of(q, ro0, jr0);
+                ra0 = rec_load(rsrc, g);
+                rb0 = rec_load(rsrc, g + 16);
             }
             while (q < qend) {
                 pin4(ra0);
                 pin4(rb0);
                 {
-                    const int g = record_of(min(q + 1, qend - 1), ro1);
-                    ra1 = rec[2 * (int64_t)g];
-                    rb1 = rec[2 * (int64_t)g + 1];
+                    const int g = record_of(min(q + 1, qend - 1), ro1, jr1);
+                    ra1 = rec_load(rsrc, g);
+                    rb1 = rec_load(rsrc, g + 16);
                 }
-                row(ra0, rb0, ro0);
+                band(ra0, rb0, ro0, jr0);
                 if (++q >= qend) break;
                 pin4(ra1);
                 pin4(rb1);
                 {
-                    const int g = record_of(min(q + 1, qend - 1), ro0);
-                    ra0 = rec[2 * (int64_t)g];
-                    rb0 = rec[2 * (int64_t)g + 1];
+                    const int g = record_of(min(q + 1, qend - 1), ro0, jr0);
+                    ra0 = rec_load(rsrc, g);
+                    rb0 = rec_load(rsrc, g + 16);
                 }
-                row(ra1, rb1, ro1);
+                band(ra1, rb1, ro1, jr1);
                 ++q;
             }
         }
@@ -1149,13 +1210,14 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                 hipLaunchKernelGGL(k_block_sums, dim3((unsigned)P->bblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step + 1, P->M, P->s.start, P->s.rec,
                                    P->s.bsum);
+                const int64_t pgrid = (P->tblocks + kXcds - 1) / kXcds * kXcds;
                 hipLaunchKernelGGL(k_pencil_scale, dim3((unsigned)P->tblocks), dim3(kBlock),
                                    P->bound_lds, st, P->dbox, P->nbox, P->s.step + 1, P->M,
                                    P->s.bsum, P->s.pscale);
-                const int64_t pgrid = (P->tblocks + kXcds - 1) / kXcds * kXcds;
                 hipLaunchKernelGGL(fn, dim3((unsigned)pgrid), dim3(big ? 1024 : 512),
                                    P->lds_bytes, st, P->dbox, P->nbox, P->s.step + 1, P->M,
-                                   P->s.start, P->s.rec, P->s.pscale, P->tblocks);
+                                   P->s.start, P->s.rec, P->s.pscale, P->tblocks,
+                                   P->np_total);
             }
             break;
         case 4:
