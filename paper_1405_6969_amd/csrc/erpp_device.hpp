@@ -99,21 +99,29 @@ __device__ __forceinline__ bool inside32(int mx, float phx, float ryz, const Dev
 // within [mlo, mhi]; lo > hi when the row is empty.  Membership along a row is
 // monotone in |mx - phi|, so the row is [ceil(phi - s*), floor(phi + s*)] for
 // the exact half-width s* (in nodes).  Its estimate s = sqrt(R^2 - ryz) / dx
-// (raw v_sqrt, multiply by 1/dx) is within 0.01 node of s* -- (guard band +
-// FP32 rounding) / (2 s dx^2) -- whenever s >= 0.01.  Each end is then settled
-// by one exact decision (inside32 semantics) at the node nearest the estimated
-// end k: the end is k if k is inside, else the next node inward.  A row with
-// s < 0.01 can hold only the node nearest phi, which both ends then test.  The
-// node set is therefore the exact one, the same in every kernel that calls this.
+// (raw v_sqrt, multiply by 1/dx) has |s^2 - s*^2| <= E / dx^2, E the FP32 error
+// of R^2 - ryz (below twice the guard band), so |s - s*| <= E / (dx^2 s); with
+// the roundings of the sqrt and of phi -/+ s the estimated ends are off by less
+// than gs / s, gs = 2 guard / dx^2 + 1e-6 smax (smax + 1).  When both estimated
+// ends phi -/+ s lie farther than that from every node, ceil and floor of them
+// are the exact ends.  Otherwise (rare: a few 1e-5 of the rows) each end is
+// settled by one exact decision (inside32 semantics) at the node k nearest the
+// estimated end: the end is k if k is inside, else the next node inward; a row
+// with s < 0.01 can hold only the node nearest phi, which both ends then test.
+// The node set is therefore the exact one, the same in every kernel that calls
+// this.
 // The box constants row_range reads, held by value so that a kernel can keep
 // them in registers across its loops.
 struct RowK {
-    float R2f, guard, idx0, dx0;
+    float R2f, guard, idx0, dx0, gs;
     int mlo0, mhi0;
 };
 
 __device__ __forceinline__ RowK row_consts(const DevBox &B) {
-    return RowK{B.R2f, B.guard, B.idxf0, B.dxf[0], B.mlo[0], B.mhi[0]};
+    const float i2 = B.idxf0 * B.idxf0;
+    const float smax = sqrtf(B.R2f * i2);
+    return RowK{B.R2f, B.guard, B.idxf0, B.dxf[0], 2.0f * B.guard * i2 + 1e-6f * smax * (smax + 1.0f),
+                B.mlo[0], B.mhi[0]};
 }
 
 __device__ __forceinline__ void row_range(float phx, float ryz, const RowK &K,
@@ -121,7 +129,13 @@ __device__ __forceinline__ void row_range(float phx, float ryz, const RowK &K,
                                           int mz, int &lo, int &hi) {
     const float rem = fmaxf(K.R2f - ryz, 0.0f);
     const float s = __builtin_amdgcn_sqrtf(rem) * K.idx0;
-    const float kl = rintf(phx - s), kh = rintf(phx + s);
+    const float el = phx - s, eh = phx + s;
+    const float kl = rintf(el), kh = rintf(eh);
+    if (fminf(fabsf(el - kl), fabsf(eh - kh)) * s >= K.gs) {
+        lo = max((int)ceilf(el), K.mlo0);
+        hi = min((int)floorf(eh), K.mhi0);
+        return;
+    }
     const float tl = (kl - phx) * K.dx0, th = (kh - phx) * K.dx0;
     const float dl = fmaf(tl, tl, ryz), dh = fmaf(th, th, ryz);
     const float below = K.R2f - K.guard, above = K.R2f + K.guard;

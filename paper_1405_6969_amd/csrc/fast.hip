@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
     // descriptor inside the loop would wait on the LDS counter)
     RowK K = row_consts(B);
     float cutv = cut;
-    asm volatile("" : "+v"(K.R2f), "+v"(K.guard), "+v"(K.idx0), "+v"(K.dx0));
+    asm volatile("" : "+v"(K.R2f), "+v"(K.guard), "+v"(K.idx0), "+v"(K.dx0), "+v"(K.gs));
     asm volatile("" : "+v"(K.mlo0), "+v"(K.mhi0), "+v"(hx), "+v"(hy), "+v"(hz), "+v"(c),
                  "+v"(cutv));
     // prefix sums of the x factors (indexed by the row ends); raw v_exp_f32, the
@@ -674,7 +674,7 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
         // on the previous row's atomics
         RowK K = row_consts(B);
         float cutv = cut;
-        asm volatile("" : "+v"(K.R2f), "+v"(K.guard), "+v"(K.idx0), "+v"(K.dx0));
+        asm volatile("" : "+v"(K.R2f), "+v"(K.guard), "+v"(K.idx0), "+v"(K.dx0), "+v"(K.gs));
         asm volatile("" : "+v"(K.mlo0), "+v"(K.mhi0), "+v"(hx), "+v"(hy), "+v"(hz), "+v"(c),
                      "+v"(cutv));
         const int ncls = s_ncls;
