@@ -81,7 +81,6 @@ void free_scratch(erpp_plan *p) {
     (void)hipFree(s.bsum);
     (void)hipFree(s.pscale);
     (void)hipFree(s.xs);
-    (void)hipFree(s.sl);
     (void)hipFree(s.part);
     (void)hipFree(s.ticket);
     (void)hipFree(s.pamp);
@@ -411,8 +410,7 @@ erpp_status erpp_plan_create(erpp_plan **out, const erpp_box *boxes, int32_t nbo
              alloc(&p->s.bsum, (size_t)std::max<int64_t>(p->nkey_total, 1)) == hipSuccess &&
              alloc(&p->s.pscale, (size_t)std::max<int64_t>(p->nrows_total, 1)) == hipSuccess &&
              alloc(&p->s.up, (size_t)np_total) == hipSuccess &&
-             alloc(&p->s.xs, (size_t)np_total) == hipSuccess &&
-             alloc(&p->s.sl, (size_t)np_total) == hipSuccess;
+             alloc(&p->s.xs, (size_t)np_total) == hipSuccess;
     if (ok && prec == ERPP_F64_PLAIN)
         ok = alloc(&p->s.pamp, 4 * (size_t)np_total) == hipSuccess &&
              alloc(&p->s.pphi, 3 * (size_t)np_total) == hipSuccess &&

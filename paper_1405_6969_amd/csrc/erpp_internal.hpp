@@ -90,10 +90,9 @@ struct Scratch {
     float4 *rec = nullptr;       // [2*np_total]    cell-sorted injection records
     float *bsum = nullptr;       // [nkey_total]    max_c |amplitude| summed over x-blocks X-1..X+1
     float *pscale = nullptr;     // [sum Ny Nz]     fixed-point scale of each scatter pencil
-    double4 *xs = nullptr;       // [np_total]      x^n in record order
-    double4 *up = nullptr;       // [np_total]      carrier at x^n in record order (FP64)
-    int32_t *sl = nullptr;       // [np_total]      record slot of each particle
-    // grid terms of the optional forces, in record order (allocated when a box
+    double4 *xs = nullptr;       // [np_total]      x^n in record order, particle index in w
+    double4 *up = nullptr;       // [np_total]      carrier at x^n in particle order (FP64)
+    // grid terms of the optional forces, in particle order (allocated when a box
     // turns on the Faxen term, the added mass or Heun): [kAux][np_total] of
     // lap u, grad u (3: d_x u, d_y u, d_z u), carrier and lap u at Heun's x*
     double4 *aux = nullptr;

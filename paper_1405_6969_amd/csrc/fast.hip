@@ -192,7 +192,6 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
                                                  const int32_t *__restrict__ rank,
                                                  float4 *__restrict__ rec,
                                                  double4 *__restrict__ xs,
-                                                 int32_t *__restrict__ sl,
                                                  double4 *__restrict__ vrec) {
     __shared__ float sP[kMaxOff + 1][kBlock];   // prefix sums of the x factors
     __shared__ int s_rng[kMaxOff];               // per mz: reachable my in [lo, hi]
@@ -293,11 +292,11 @@ __global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, 
     const uint32_t ijk = (uint32_t)b[0] | ((uint32_t)b[1] << 11) | ((uint32_t)b[2] << 22);
     rec[2 * slotr] = make_float4(phx, phy, phz, __uint_as_float(ijk));
     rec[2 * slotr + 1] = make_float4(ax, ay, az, __int_as_float((int)p));
-    // the current position x^n, in record order for the carrier gather
-    xs[slotr] = make_double4(x0, x1, x2, 0.0);
+    // the current position x^n, in record order for the carrier gather, with the
+    // particle index (exact in a double) for the gather's writes
+    xs[slotr] = make_double4(x0, x1, x2, (double)p);
     // and v^n for Heun's second stage (x* = x^n + dt v^n), evaluated by the gather
     if (vrec && B.integ == 2) vrec[slotr] = make_double4(B.v[p], B.v[np + p], B.v[2 * np + p], 0.0);
-    sl[B.poff + p] = (int32_t)slotr;
 }
 
 __device__ __forceinline__ int wrap_index(int i, int N) {
@@ -863,10 +862,11 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
 // in M steps, so neighbouring threads read neighbouring carrier nodes and the
 // field streams through L2 about once, instead of eight scattered rows per
 // particle.  x^n arrives in record order from the evaluation kernel; the FP64
-// trilinear value (plus the mean shear) is stored in record order too.
+// trilinear value (plus the mean shear) is stored in particle order, where the
+// update reads it.
 // LAP: also lap u at x^n (Faxen term, added mass); GRAD: grad u at x^n (added
 // mass); HEUN: the carrier (and, with LAP, lap u) at Heun's x* = x^n + dt v^n.
-// These go to aux[k][record], k = 0 lap, 1..3 grad (d_x u, d_y u, d_z u), 4 u(x*),
+// These go to aux[k][particle], k = 0 lap, 1..3 grad (d_x u, d_y u, d_z u), 4 u(x*),
 // 5 lap u(x*), for the boxes that use them.
 template <bool LAP, bool GRAD, bool HEUN>
 __global__ void __launch_bounds__(kBlock) k_gather_sorted(const DevBox *__restrict__ Bs, int nbox,
@@ -894,7 +894,9 @@ __global__ void __launch_bounds__(kBlock) k_gather_sorted(const DevBox *__restri
     double xp[3] = {x4.x, x4.y, x4.z};
     double u[3];
     trilinear<float>(B, (const float *)B.u, xp, u);
-    const int64_t slot = B.poff + r;
+    // results go to the particle's own slot, so that the update reads them in
+    // particle order (one line per 2 particles rather than one per particle)
+    const int64_t slot = B.poff + (int64_t)x4.w;
     up[slot] = make_double4(u[0], u[1], u[2], 0.0);
     const bool lap = LAP && (B.fax != 0.0 || B.am_mf != 0.0 || B.bs_k != 0.0);
     const bool grad = GRAD && B.am_mf != 0.0;
@@ -912,7 +914,7 @@ __global__ void __launch_bounds__(kBlock) k_gather_sorted(const DevBox *__restri
             aux[(1 + j) * npt + slot] = make_double4(g[j], g[3 + j], g[6 + j], 0.0);
     }
     if (HEUN && B.integ == 2) {
-        const double4 v4 = vrec[slot];
+        const double4 v4 = vrec[B.poff + r];
         const double x2[3] = {xp[0] + dt * v4.x, xp[1] + dt * v4.y, xp[2] + dt * v4.z};
         double u2[3];
         trilinear<float>(B, (const float *)B.u, x2, u2);
@@ -1014,7 +1016,6 @@ __global__ void __launch_bounds__(kBlock) k_update(const DevBox *__restrict__ Bs
                                                    const int64_t *__restrict__ stepp, int M,
                                                    double dt, int selfc,
                                                    const double4 *__restrict__ upc,
-                                                   const int32_t *__restrict__ sl,
                                                    const double4 *__restrict__ aux, int64_t npt) {
     const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_p; });
     const DevBox &B = Bs[bi];
@@ -1024,10 +1025,10 @@ __global__ void __launch_bounds__(kBlock) k_update(const DevBox *__restrict__ Bs
     const int64_t np = B.np;
     double xp[3] = {B.x[p], B.x[np + p], B.x[2 * np + p]};
     double up[3];
-    // grid terms gathered in record order by k_gather_sorted once records exist;
+    // grid terms gathered by k_gather_sorted (in particle order) once records exist;
     // the first M steps (no records yet) interpolate in place
     const bool rec = n >= M;
-    const int64_t sr = rec ? (int64_t)sl[B.poff + p] : 0;
+    const int64_t sr = B.poff + p;
     if (rec) {
         const double4 g = upc[sr];
         up[0] = g.x;
@@ -1193,7 +1194,7 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
             if (P->np_total > 0)
                 hipLaunchKernelGGL(k_eval, dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step + 1, P->M, P->s.start, P->s.rank,
-                                   P->s.rec, P->s.xs, P->s.sl, P->s.vrec);
+                                   P->s.rec, P->s.xs, P->s.vrec);
             break;
         case 3:
             {
@@ -1247,7 +1248,7 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                 hipLaunchKernelGGL(upd,
                                    dim3((unsigned)P->pblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step + 1, P->M, P->dt, P->self_correction,
-                                   P->s.up, P->s.sl, P->s.aux, P->np_total);
+                                   P->s.up, P->s.aux, P->np_total);
                 if (am) return mark_memory_terms(P, st);
             }
             break;
