@@ -380,7 +380,7 @@ __global__ void __launch_bounds__(kBlock) k_pencil_scale(const DevBox *__restric
                                                          float *__restrict__ pscale) {
     if (*stepp < M) return;
     extern __shared__ float win[];              // [WZ][WY][kBoundXChunk] of bsum
-    __shared__ int s_dy[256], s_dz[256];
+    __shared__ int s_off[256];                  // window row offset of each class
     __shared__ int s_wcnt[kBlock / 64];
     __shared__ float s_max[kBlock / 64];
     const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_t; });
@@ -420,8 +420,9 @@ __global__ void __launch_bounds__(kBlock) k_pencil_scale(const DevBox *__restric
         }
         if (reach) {
             const int i = before + __popcll(mask & ((1ull << lane) - 1ull));
-            s_dy[i] = mlo1 + k % ny;
-            s_dz[i] = mlo2 + k / ny;
+            // class (dy, dz) = (mlo1 + k mod ny, mlo2 + k / ny): the window row of
+            // pencil row (y, z) is (z + mhi2 - dz) WY + y + mhi1 - dy
+            s_off[i] = (mhi2 - (mlo2 + k / ny)) * WY + mhi1 - (mlo1 + k % ny);
         }
         ncls = total;
         __syncthreads();
@@ -434,7 +435,7 @@ __global__ void __launch_bounds__(kBlock) k_pencil_scale(const DevBox *__restric
         // are zero), its (wy, wz) advanced without a division per entry
         {
             constexpr int kRowStep = kBlock / kBoundXChunk;
-            constexpr int kBatch = 8;
+            constexpr int kBatch = 32;
             const int X = tid & (kBoundXChunk - 1);
             const int Xc = min(X, nx - 1);
             const int total = WZ * WY;
@@ -469,22 +470,32 @@ __global__ void __launch_bounds__(kBlock) k_pencil_scale(const DevBox *__restric
             }
         }
         __syncthreads();
-        // four x-blocks per thread (128-bit LDS reads; entries past nx are zero)
+        // four x-blocks per output (128-bit LDS reads; entries past nx are zero); two
+        // neighbouring lanes per output, each summing every other class (two
+        // accumulators), combined in a fixed order
         const int nq = (nx + 3) / 4;
-        for (int k = tid; k < e1 * e2 * nq; k += kBlock) {
+        for (int k2 = tid; k2 < 2 * e1 * e2 * nq; k2 += kBlock) {
+            const int h = k2 & 1, k = k2 >> 1;
             const int Xq = k % nq, r = k / nq;
             const int y = r % e1, z = r / e1;
-            float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll 8
-            for (int ci = 0; ci < ncls; ++ci) {
-                const float4 v = *(const float4 *)&win[((z + mhi2 - s_dz[ci]) * WY +
-                                                        (y + mhi1 - s_dy[ci])) * kBoundXChunk +
-                                                       4 * Xq];
-                sum.x += v.x;
-                sum.y += v.y;
-                sum.z += v.z;
-                sum.w += v.w;
+            const float *wp = win + (z * WY + y) * kBoundXChunk + 4 * Xq;
+            float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
+            int ci = h;
+            for (; ci + 2 < ncls; ci += 4) {
+                const float4 v0 = *(const float4 *)(wp + s_off[ci] * kBoundXChunk);
+                const float4 v1 = *(const float4 *)(wp + s_off[ci + 2] * kBoundXChunk);
+                a0.x += v0.x; a0.y += v0.y; a0.z += v0.z; a0.w += v0.w;
+                a1.x += v1.x; a1.y += v1.y; a1.z += v1.z; a1.w += v1.w;
             }
+            if (ci < ncls) {
+                const float4 v0 = *(const float4 *)(wp + s_off[ci] * kBoundXChunk);
+                a0.x += v0.x; a0.y += v0.y; a0.z += v0.z; a0.w += v0.w;
+            }
+            float4 sum = make_float4(a0.x + a1.x, a0.y + a1.y, a0.z + a1.z, a0.w + a1.w);
+            sum.x += __shfl_xor(sum.x, 1, 64);
+            sum.y += __shfl_xor(sum.y, 1, 64);
+            sum.z += __shfl_xor(sum.z, 1, 64);
+            sum.w += __shfl_xor(sum.w, 1, 64);
             bmax = fmaxf(bmax, fmaxf(fmaxf(sum.x, sum.y), fmaxf(sum.z, sum.w)));
         }
         __syncthreads();
