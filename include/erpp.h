@@ -224,12 +224,14 @@ erpp_status erpp_plan_tune(erpp_plan *plan, const char *cache_path, void *stream
 erpp_status erpp_plan_bins(const erpp_plan *plan, int32_t ibox, int32_t *nbin);
 
 /* Bin `pos` ([3][np] device FP64 positions of box ibox, e.g. x^n or a ring
- * level) by grid cell (stage 1; the cell rule of Sec. 2.4's lattice, nodes at
- * i dx): key[p] = (k Ny + j) Nx + i is the cell of the wrapped position
- * (i = min(floor(x/dx), N-1), per dimension); bin_start[0..ncell] is the
- * exclusive scan of the cell counts and perm lists the particles grouped by cell
- * in ascending key order (order inside a cell unspecified).  key, perm,
- * bin_start: device, caller-owned, sizes np, np, ncell+1. */
+ * level) by grid cell (stage 1).  The binning is a locality structure of this
+ * library, not a step of the paper; its cell rule follows the grid the forcing
+ * lives on (nodes at i dx, dx = L/N): key[p] = (k Ny + j) Nx + i is the cell of
+ * the wrapped position (i = min(floor(x/dx), N-1), per dimension);
+ * bin_start[0..ncell] is the exclusive scan of the cell counts and perm lists
+ * the particles grouped by cell in ascending key order (order inside a cell
+ * unspecified).  key, perm, bin_start: device, caller-owned, sizes np, np,
+ * ncell+1. */
 erpp_status erpp_bin(erpp_plan *plan, int32_t ibox, const double *pos, int32_t *key,
                      int32_t *perm, int32_t *bin_start, void *stream);
 
@@ -250,14 +252,31 @@ erpp_status erpp_bin_static(const int32_t n[3], const double L[3], int64_t np, c
                             int32_t *key, int32_t *perm, int32_t *bin_start, void *stream);
 
 /* Stages 1-3 for every box: write f for step `step` from ring level step-M
- * (f = 0 when step < M).  The ring is only read. */
+ * (f = 0 when step < M).  f is the regularised forcing of Sec. 2.4 (eq.
+ * ns_regularized_filtered): each particle's drag of M steps earlier (Sec. 2.3,
+ * the delay eps_R = M dt), spread as -D/(rho_f) times the Gaussian of width
+ * sigma_R cut at 3 sigma (Sec. 3.2), normalised per particle over the nodes it
+ * covers so that rho_f dV sum(f) = -sum(D).  f: [3][Nz][Ny][Nx] FP32 (fast) or
+ * FP64 (plain) device array of each box, overwritten.  The ring is only read.
+ * Errors: ERPP_EINVAL for a NULL plan or step < 0; ERPP_EHIP on a launch
+ * failure. */
 erpp_status erpp_scatter(erpp_plan *plan, int64_t step, void *stream);
 
-/* Stage 4 for every box: u_p = trilinear(u, x) + S (y - Ly/2) e_x, FP64,
- * [3][np] per box, boxes concatenated in plan order (device, caller-owned). */
+/* Stage 4 for every box: the carrier at the particle (Sec. 2.5, the fluid
+ * velocity in the drag of eq. force_stokes_drag), u_p = trilinear(u, x) +
+ * S (y - Ly/2) e_x at the current positions x, FP64, [3][np] per box, boxes
+ * concatenated in plan order (device, caller-owned).  Errors: ERPP_EINVAL for a
+ * NULL plan or u_p (with particles); ERPP_EHIP on a launch failure. */
 erpp_status erpp_gather(erpp_plan *plan, double *u_p, void *stream);
 
-/* Stages 1-5 for every box (one coupling step n = step). */
+/* Stages 1-5 for every box: one coupling step n = step.  The forcing of
+ * erpp_scatter, then per particle the drag of Sec. 2.5 (eq. force_stokes_drag,
+ * with the particle's own disturbance, App. E eq. disturbance_velo from the
+ * injection of level n-1-M, removed from the carrier), the ring write of (x^n,
+ * D^n) at slot n mod (M+1), and the step of eq. particle_motion (explicit Euler
+ * unless erpp_plan_set_integrator chose otherwise), with periodic wrap.  x, v,
+ * the ring and f of every box are updated in place.  Errors: ERPP_EINVAL for a
+ * NULL plan or step < 0; ERPP_EHIP on a launch failure. */
 erpp_status erpp_step(erpp_plan *plan, int64_t step, void *stream);
 
 /* Steps step0 .. step0+nsteps-1.  use_graph = 1 captures the step once in a

@@ -11,7 +11,8 @@
 //                lap(phi) = -div(u*), u = u* + grad(phi)), inverse FFT along z
 //   k_fy         inverse FFT along y
 //   k_fx_c2r     inverse real FFT along x into u
-// Each pass stages its lines in LDS and runs a radix-2 transform there.  Other
+// Each pass stages its lines in LDS and runs a Stockham transform there (radix 8
+// and 4 passes, natural order in and out).  Other
 // sizes use hipFFT, four launches:
 //   k_fluid_force     u += dt f
 //   forward R2C       U = FFT(u), three components batched (may overwrite u)
