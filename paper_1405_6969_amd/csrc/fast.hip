@@ -62,8 +62,9 @@ __global__ void __launch_bounds__(kBlock) k_bin_count(const DevBox *__restrict__
 
 // ------------------------------------------------------------------ scan ----
 // start[0..n] = exclusive scan of count[0..n), count reset to zero.  Two
-// launches: per-chunk sums (the last workgroup also scans them), then the
-// per-chunk scan with its offset.  Chunks of kScanChunk counters, 256 x 16.
+// launches: per-chunk sums, then the per-chunk scan, each workgroup adding the
+// sum of the chunk sums before its own (integer sums: the order does not
+// matter).  Chunks of kScanChunk counters, 256 threads.
 
 __device__ __forceinline__ int wave_incl_scan(int x) {
     const int lane = threadIdx.x & 63;
@@ -92,16 +93,10 @@ __device__ __forceinline__ int block_excl_scan(int v, int *sw, int nw, int *tota
     return pre + x - v;
 }
 
-// Per-chunk sums; the last workgroup to finish (device-scope ticket) scans them
-// in place (part[nchunk] = total), resets the ticket, and -- for the step's own
-// binning -- publishes the step index: stepp[1] = stepp[0] (read by the kernels
-// after the scan), stepp[0] += 1 (the next step).
+// Per-chunk sums into part[chunk].
 __global__ void __launch_bounds__(256) k_scan_reduce(const int32_t *__restrict__ count,
-                                                     int64_t n, int32_t *__restrict__ part,
-                                                     int64_t nchunk, int32_t *__restrict__ ticket,
-                                                     int64_t *__restrict__ stepp) {
+                                                     int64_t n, int32_t *__restrict__ part) {
     __shared__ int sw[4];
-    __shared__ int s_last;
     const int64_t base = (int64_t)blockIdx.x * kScanChunk;
     int s = 0;
 #pragma unroll
@@ -112,43 +107,22 @@ __global__ void __launch_bounds__(256) k_scan_reduce(const int32_t *__restrict__
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = sw[0] + sw[1] + sw[2] + sw[3];
-        __threadfence();
-        s_last = atomicAdd(ticket, 1) == (int)(nchunk - 1);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    const int64_t per = (nchunk + 255) / 256;
-    const int64_t a = threadIdx.x * per;
-    const int64_t e = (a + per < nchunk) ? a + per : nchunk;
-    int t = 0;
-    for (int64_t i = a; i < e; ++i) t += part[i];
-    int total;
-    int run = block_excl_scan(t, sw, 4, &total);
-    for (int64_t i = a; i < e; ++i) {
-        const int c = part[i];
-        part[i] = run;
-        run += c;
-    }
-    if (threadIdx.x == 0) {
-        part[nchunk] = total;
-        *ticket = 0;
-        if (stepp) {
-            const int64_t cur = stepp[0];
-            stepp[1] = cur;
-            stepp[0] = cur + 1;
-        }
-    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sw[0] + sw[1] + sw[2] + sw[3];
 }
 
+// The last workgroup also writes start[n] (the total); workgroup 0 publishes
+// the step index for the step's own binning: stepp[1] = stepp[0] (read by the
+// kernels after the scan), stepp[0] += 1 (the next step).
 __global__ void __launch_bounds__(256) k_scan_down(int32_t *__restrict__ count, int64_t n,
                                                    const int32_t *__restrict__ part,
-                                                   int64_t nchunk, int32_t *__restrict__ start) {
-    // chunk staged in LDS with one pad word per 16 (thread t owns 16 consecutive)
-    __shared__ int buf[kScanChunk + kScanChunk / 16];
-    __shared__ int sw[4];
+                                                   int64_t nchunk, int32_t *__restrict__ start,
+                                                   int64_t *__restrict__ stepp) {
+    // chunk staged in LDS with one pad word per kRun (thread t owns kRun consecutive
+    // counters; the odd stride kRun + 1 keeps the row reads off each other's banks)
+    constexpr int kRun = kScanChunk / 256;
+    static_assert(kScanChunk % 256 == 0 && (kRun & (kRun - 1)) == 0, "scan chunk: 256 x 2^k");
+    __shared__ int buf[kScanChunk + kScanChunk / kRun];
+    __shared__ int sw[4], sw2[4];
     const int64_t base = (int64_t)blockIdx.x * kScanChunk;
     const int t = threadIdx.x;
     int cv[kScanChunk / 256];
@@ -162,25 +136,36 @@ __global__ void __launch_bounds__(256) k_scan_down(int32_t *__restrict__ count, 
         const int k = j * 256 + t;
         const int64_t i = base + k;
         if (i < n) count[i] = 0;
-        buf[k + (k >> 4)] = cv[j];
+        buf[k + k / kRun] = cv[j];
     }
+    // offset of the chunk: the sum of the chunk sums before it
+    int pre = 0;
+    for (int64_t c = t; c < (int64_t)blockIdx.x; c += 256) pre += part[c];
+    for (int off = 32; off > 0; off >>= 1) pre += __shfl_xor(pre, off, 64);
+    if ((t & 63) == 0) sw2[t >> 6] = pre;
     __syncthreads();
+    const int off = sw2[0] + sw2[1] + sw2[2] + sw2[3];
     int s = 0;
-    for (int j = 0; j < 16; ++j) s += buf[t * 17 + j];
+    for (int j = 0; j < kRun; ++j) s += buf[t * (kRun + 1) + j];
     int total;
-    int run = block_excl_scan(s, sw, 4, &total) + part[blockIdx.x];
-    for (int j = 0; j < 16; ++j) {
-        const int c = buf[t * 17 + j];
-        buf[t * 17 + j] = run;
+    int run = block_excl_scan(s, sw, 4, &total) + off;
+    for (int j = 0; j < kRun; ++j) {
+        const int c = buf[t * (kRun + 1) + j];
+        buf[t * (kRun + 1) + j] = run;
         run += c;
     }
     __syncthreads();
     for (int j = 0; j < kScanChunk / 256; ++j) {
         const int k = j * 256 + t;
         const int64_t i = base + k;
-        if (i < n) start[i] = buf[k + (k >> 4)];
+        if (i < n) start[i] = buf[k + k / kRun];
     }
-    if (blockIdx.x == 0 && t == 0) start[n] = part[nchunk];
+    if (blockIdx.x == nchunk - 1 && t == 0) start[n] = off + total;
+    if (blockIdx.x == 0 && t == 0 && stepp) {
+        const int64_t cur = stepp[0];
+        stepp[1] = cur;
+        stepp[0] = cur + 1;
+    }
 }
 
 // ------------------------------------------------------------------ eval ----
@@ -1167,10 +1152,10 @@ hipError_t scan_counts(int32_t *count, int64_t n, int32_t *start, int32_t *part,
                        int64_t *stepp, hipStream_t st) {
     const int64_t nchunk = (n + kScanChunk - 1) / kScanChunk;
     if (nchunk == 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nchunk), dim3(256), 0, st, count, n, part,
-                       nchunk, ticket, stepp);
+    (void)ticket;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nchunk), dim3(256), 0, st, count, n, part);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nchunk), dim3(256), 0, st, count, n, part,
-                       nchunk, start);
+                       nchunk, start, stepp);
     return hipGetLastError();
 }
 
