@@ -63,6 +63,9 @@ def parse():
                     help="skip the 256^3 target of the shear workload (c3cube)")
     ap.add_argument("--no-coupled", action="store_true",
                     help="skip the two-way coupled run (coupling step + fluid step)")
+    ap.add_argument("--rows-per-item", type=int, default=0, metavar="R",
+                    help="stencil rows per work item of the scatter (2..4; default: the "
+                         "autotuner's choice, or 3 with --tile / --no-tune)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (the reference kernel "
                          "for scaling HBM counter readings)")
@@ -148,6 +151,8 @@ def measure_fast(boxes, w, K, W, args, erpp, torch, tile=None, stage_steps=10):
         plan.set_tile(tuple(int(a) for a in args.tile.split(",")))
     elif not args.no_tune:
         plan.tune(None)
+    if getattr(args, "rows_per_item", 0):
+        plan.set_rows_per_item(args.rows_per_item)
     tile = plan.get_tile()
     steps_done = prefill
     plan.run(steps_done, W, graph=True)          # capture, then W replays (untimed)
@@ -191,7 +196,8 @@ def measure_fast(boxes, w, K, W, args, erpp, torch, tile=None, stage_steps=10):
             "lds_atomic_tops": round(lds_ops / (stage_ms[dom] * 1e-3) / 1e12, 3),
             "lds_peak_tops": round(LDS_PEAK_TOPS, 2)}
     step_gbs = step_bytes / (ms_step * 1e-3) / 1e9
-    res = {"value": value, "ms_per_step": ms_step, "tile": list(tile), "prefill": prefill,
+    res = {"value": value, "ms_per_step": ms_step, "tile": list(tile),
+           "rows_per_item": plan.get_rows_per_item(), "prefill": prefill,
            "warmup": W, "steps": K, "steps_done": steps_done,
            "hbm_frac_step": round(step_gbs / HBM_PEAK_GBS, 4),
            "algorithmic_bytes_per_step": step_bytes,
@@ -297,6 +303,7 @@ def main():
                   "value": round(tres["value"], 1), "unit": "particle-steps/s",
                   "ms_per_step": round(tres["ms_per_step"], 6), "steps": Kt,
                   "warmup": W, "prefill_steps": tres["prefill"], "tile": tres["tile"],
+                  "rows_per_item": tres["rows_per_item"],
                   "hbm_frac_step": tres["hbm_frac_step"],
                   "algorithmic_bytes_per_step": tres["algorithmic_bytes_per_step"],
                   "stage_us": tres["stage_us"], "roofline": tres["roofline"],
@@ -335,7 +342,8 @@ def main():
         "config": {"workload": w.name, "boxes": len(boxes),
                    "grid": list(boxes[0].n) if len(boxes) == 1 else "ensemble",
                    "particles": np_tot, "M": M, "dt": dt, "sigma_dx": boxes[0].spec.sigma_dx,
-                   "tile": list(tile), "graph": True, "integration": "f64",
+                   "tile": list(tile), "rows_per_item": res["rows_per_item"], "graph": True,
+                   "integration": "f64",
                    "prefill_steps": res["prefill"]},
         "hbm_frac_step": res["hbm_frac_step"],
         "algorithmic_bytes_per_step": res["algorithmic_bytes_per_step"],

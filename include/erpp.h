@@ -139,6 +139,15 @@ erpp_status erpp_plan_create(erpp_plan **plan, const erpp_box *boxes, int32_t nb
 erpp_status erpp_plan_set_tile(erpp_plan *plan, const int32_t tile[3]);
 erpp_status erpp_plan_get_tile(const erpp_plan *plan, int32_t tile[3]);
 
+/* Work item of the ERPP_F32_FAST scatter: one lane deposits `rows` consecutive
+ * stencil rows (dy, one dz) of one particle, so a wavefront pass covers 64
+ * particles and 64 rows times `rows`: fewer rows per item, more particles per
+ * wavefront for the same rows.  rows in [2, 4] (default 3), else ERPP_EINVAL.
+ * The forcing does not depend on it (exact integer sums).  Invalidates a
+ * captured graph.  Accepted and ignored on ERPP_F64_PLAIN plans. */
+erpp_status erpp_plan_set_rows_per_item(erpp_plan *plan, int32_t rows);
+erpp_status erpp_plan_get_rows_per_item(const erpp_plan *plan, int32_t *rows);
+
 /* Body acceleration of the particles of box `ibox`, (m_p - m_f) g / m_p
  * (Sec. 2.5, eq. particle_motion: gravity acts on the particle minus its
  * displaced fluid mass).  It enters the velocity update only,
@@ -211,7 +220,8 @@ erpp_status erpp_plan_set_integrator(erpp_plan *plan, erpp_integrator kind);
 
 /* Autotuner (ERPP_F32_FAST): times every candidate pencil shape on the plan's own
  * boxes with the scatter of step n, the step following the last one run (the
- * ring, positions and velocities are only read) and keeps the fastest.
+ * ring, positions and velocities are only read) and keeps the fastest; then, at
+ * that pencil, the rows per work item (erpp_plan_set_rows_per_item).
  * Afterwards the step counter is n again and every box's f holds the forcing of
  * step n, which the next erpp_step(n) writes again.  With cache_path != NULL the
  * choice is read from / appended to that text file, keyed by the geometry; a

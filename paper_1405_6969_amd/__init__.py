@@ -24,7 +24,8 @@ EXPORTS = ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile", "erpp
            "erpp_stage_times", "erpp_plan_destroy", "erpp_status_string", "erpp_last_error",
            "erpp_fluid_create", "erpp_fluid_step", "erpp_fluid_destroy", "erpp_run_coupled",
            "erpp_plan_set_body_force", "erpp_plan_set_integrator", "erpp_plan_set_faxen",
-           "erpp_plan_set_added_mass", "erpp_bin_static", "erpp_plan_set_basset"]
+           "erpp_plan_set_added_mass", "erpp_bin_static", "erpp_plan_set_basset",
+           "erpp_plan_set_rows_per_item", "erpp_plan_get_rows_per_item"]
 
 
 class ErppError(RuntimeError):
@@ -85,12 +86,15 @@ def load(path: str = LIB_PATH):
     lib.erpp_plan_set_added_mass.argtypes = [vp, i32, d, vp]
     lib.erpp_bin_static.argtypes = [C.POINTER(i32), C.POINTER(d), i64, vp, vp, vp, vp, vp]
     lib.erpp_plan_set_basset.argtypes = [vp, i32, d, vp]
+    lib.erpp_plan_set_rows_per_item.argtypes = [vp, i32]
+    lib.erpp_plan_get_rows_per_item.argtypes = [vp, C.POINTER(i32)]
     for name in ["erpp_plan_create", "erpp_plan_set_tile", "erpp_plan_get_tile",
                  "erpp_plan_tune", "erpp_plan_bins", "erpp_bin", "erpp_scatter", "erpp_gather",
                  "erpp_step", "erpp_run", "erpp_stage_times", "erpp_fluid_create",
                  "erpp_fluid_step", "erpp_run_coupled", "erpp_plan_set_body_force",
                  "erpp_plan_set_integrator", "erpp_plan_set_faxen", "erpp_plan_set_added_mass",
-                 "erpp_bin_static", "erpp_plan_set_basset"]:
+                 "erpp_bin_static", "erpp_plan_set_basset", "erpp_plan_set_rows_per_item",
+                 "erpp_plan_get_rows_per_item"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -280,6 +284,16 @@ class Plan:
         t = (C.c_int32 * 3)()
         _check(self.lib.erpp_plan_get_tile(self.h, t), "erpp_plan_get_tile")
         return tuple(t)
+
+    def set_rows_per_item(self, rows: int):
+        _check(self.lib.erpp_plan_set_rows_per_item(self.h, int(rows)),
+               "erpp_plan_set_rows_per_item")
+
+    def get_rows_per_item(self) -> int:
+        r = C.c_int32()
+        _check(self.lib.erpp_plan_get_rows_per_item(self.h, C.byref(r)),
+               "erpp_plan_get_rows_per_item")
+        return int(r.value)
 
     def tune(self, cache_path: Optional[str] = None, stream=None):
         cp = cache_path.encode() if cache_path else None

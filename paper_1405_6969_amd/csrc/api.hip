@@ -460,6 +460,24 @@ erpp_status erpp_plan_set_tile(erpp_plan *p, const int32_t tile[3]) {
     return upload_boxes(p);
 }
 
+erpp_status erpp_plan_set_rows_per_item(erpp_plan *p, int32_t rows) {
+    if (!p) return fail(ERPP_EINVAL, "plan is NULL");
+    if (rows < erpp::kMinBand || rows > erpp::kMaxBand)
+        return fail(ERPP_EINVAL, "rows per item %d outside [%d, %d]", rows, erpp::kMinBand,
+                    erpp::kMaxBand);
+    if (rows != p->band) {
+        p->band = rows;
+        drop_graph(p);   // the captured step holds the scatter instance
+    }
+    return ERPP_OK;
+}
+
+erpp_status erpp_plan_get_rows_per_item(const erpp_plan *p, int32_t *rows) {
+    if (!p || !rows) return fail(ERPP_EINVAL, "NULL argument");
+    *rows = p->band;
+    return ERPP_OK;
+}
+
 erpp_status erpp_plan_set_body_force(erpp_plan *p, int32_t ibox, const double g[3]) {
     if (!p) return fail(ERPP_EINVAL, "plan is NULL");
     if (ibox < 0 || ibox >= p->nbox) return fail(ERPP_EINVAL, "ibox %d out of range", ibox);
@@ -737,7 +755,7 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
     hipStream_t st = as_stream(stream);
     // geometry key
     std::ostringstream key;
-    key << "v5 M" << p->M << " nbox" << p->nbox;
+    key << "v7 M" << p->M << " nbox" << p->nbox;
     for (const auto &B : p->hbox)
         key << " " << B.n[0] << "x" << B.n[1] << "x" << B.n[2] << ":" << B.np << ":" << B.mlo[0]
             << "," << B.mhi[0];
@@ -748,10 +766,13 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
         while (std::getline(in, line)) {
             size_t bar = line.rfind('|');
             if (bar == std::string::npos || line.substr(0, bar) != k) continue;
-            int32_t t[3];
-            if (std::sscanf(line.c_str() + bar + 1, "%d %d %d", &t[0], &t[1], &t[2]) == 3 &&
-                check_tile(t) == ERPP_OK)
-                return erpp_plan_set_tile(p, t);
+            int32_t t[3], rows = 0;
+            if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d", &t[0], &t[1], &t[2], &rows) ==
+                    4 &&
+                check_tile(t) == ERPP_OK && rows >= erpp::kMinBand && rows <= erpp::kMaxBand) {
+                erpp_status s = erpp_plan_set_rows_per_item(p, rows);
+                return s == ERPP_OK ? erpp_plan_set_tile(p, t) : s;
+            }
         }
     }
     static const int32_t cand[][3] = {{512, 16, 1},  {512, 8, 2},   {512, 8, 1},  {512, 4, 4},
@@ -777,24 +798,43 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
                     "least M = %d steps first)", (long long)n, p->M);
     }
     erpp_status status = ERPP_OK;
-    for (int c = 0; c < ncand && status == ERPP_OK; ++c) {
-        if (check_tile(cand[c]) != ERPP_OK) continue;
-        if (erpp_plan_set_tile(p, cand[c]) != ERPP_OK) continue;   // does not fit these boxes
-        status = erpp_scatter(p, n, stream);   // warm-up
-        if (status != ERPP_OK) break;
+    // time the scatter of step n (warm-up, then 5 launches); ms < 0 on failure
+    auto time_scatter = [&](float &ms) {
+        status = erpp_scatter(p, n, stream);
+        if (status != ERPP_OK) return;
         (void)hipEventRecord(a, st);
         const int reps = 5;
         for (int r = 0; r < reps && status == ERPP_OK; ++r) status = erpp_scatter(p, n, stream);
         (void)hipEventRecord(b, st);
         if (hipEventSynchronize(b) != hipSuccess) {
             status = fail(ERPP_EHIP, "autotuner synchronisation");
-            break;
+            return;
         }
-        float ms = 0.f;
         (void)hipEventElapsedTime(&ms, a, b);
-        if (ms < best_ms) {
+    };
+    // pencils at the default rows per item, then the rows per item (the number of
+    // particles a wavefront pass covers for the same rows) at the best pencil
+    int32_t best_rows = erpp::kDefaultBand;
+    if (p->band != best_rows) status = erpp_plan_set_rows_per_item(p, best_rows);
+    for (int c = 0; c < ncand && status == ERPP_OK; ++c) {
+        if (check_tile(cand[c]) != ERPP_OK) continue;
+        if (erpp_plan_set_tile(p, cand[c]) != ERPP_OK) continue;   // does not fit these boxes
+        float ms = 0.f;
+        time_scatter(ms);
+        if (status == ERPP_OK && ms < best_ms) {
             best_ms = ms;
             std::memcpy(best, cand[c], sizeof best);
+        }
+    }
+    if (status == ERPP_OK) status = erpp_plan_set_tile(p, best);
+    for (int rows = erpp::kMinBand; rows <= erpp::kMaxBand && status == ERPP_OK; ++rows) {
+        if (rows == erpp::kDefaultBand) continue;
+        status = erpp_plan_set_rows_per_item(p, rows);
+        float ms = 0.f;
+        if (status == ERPP_OK) time_scatter(ms);
+        if (status == ERPP_OK && ms < best_ms) {
+            best_ms = ms;
+            best_rows = rows;
         }
     }
     (void)hipEventDestroy(a);
@@ -805,10 +845,13 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
         if (e != hipSuccess && status == ERPP_OK) status = hip_fail(e, "erpp_plan_tune");
     }
     if (status != ERPP_OK) return status;
-    status = erpp_plan_set_tile(p, best);
+    status = erpp_plan_set_rows_per_item(p, best_rows);
+    if (status == ERPP_OK) status = erpp_plan_set_tile(p, best);
     if (status == ERPP_OK && cache_path) {
         std::ofstream o(cache_path, std::ios::app);
-        if (o) o << k << "|" << best[0] << " " << best[1] << " " << best[2] << "\n";
+        if (o)
+            o << k << "|" << best[0] << " " << best[1] << " " << best[2] << " " << best_rows
+              << "\n";
     }
     return status;
 }

@@ -14,6 +14,9 @@ namespace erpp {
 constexpr int kMaxTileY = 64;        // scatter pencil: T1 x T2 nodes in (y, z), all of x
 constexpr int kMaxTileZ = 8;
 constexpr int kBlock = 256;          // threads per block of particle kernels
+constexpr int kMinBand = 2;          // rows per work item of the scatter: the
+constexpr int kMaxBand = 4;          //   instances built
+constexpr int kDefaultBand = 3;
 constexpr int kScanChunk = 4096;     // counters per block of the device-wide scan
 constexpr int kXBlockShift = 4;      // step binning: x-blocks of 16 cells per cell row
 constexpr int kAux = 6;              // record-order grid terms: lap, grad x3, u(x*), lap(x*)
@@ -132,6 +135,7 @@ struct erpp_plan {
     int64_t pblocks_rows = 0;    // plain scatter: blocks over (particle,row)
     erpp::Scratch s;
     size_t lds_bytes = 0;
+    int32_t band = erpp::kDefaultBand;  // scatter: stencil rows per work item (lane)
     size_t bound_lds = 0;        // dynamic LDS of the pencil-scale kernel
     // graph of one step (step index read from s.step)
     hipGraph_t graph = nullptr;

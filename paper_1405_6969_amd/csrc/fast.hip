@@ -498,9 +498,9 @@ __global__ void __launch_bounds__(kBlock) k_pencil_scale(const DevBox *__restric
 
 // --------------------------------------------------------------- scatter ----
 
-// Rows of one work item of the scatter: a band of kBand consecutive stencil rows
-// dy of one plane dz (all lanes of a pass take the same band).
-constexpr int kBand = 3;
+// Rows of one work item of the scatter: a band of KB (kMinBand..kMaxBand, the
+// plan's rows per item) consecutive stencil rows dy of one plane dz (all lanes of
+// a pass take the same band).
 
 // Fourth descriptor word of a raw (unformatted, unswizzled) gfx9 buffer resource.
 constexpr int kBufferWord3 = 0x00020000;
@@ -535,11 +535,11 @@ __device__ __forceinline__ uint32_t fixed32(float v) {
 // particles whose row lies on pencil plane z are those with b2 = o2 + z - dz and
 // b1 in [o1 - dy, o1 - dy + e1): since records are sorted by cell and a pencil
 // spans all of x, that is one contiguous record range (two when it wraps in y).
-// Classes are taken kBand rows at a time (consecutive dy of one dz): a wave
+// Classes are taken KB rows at a time (consecutive dy of one dz): a wave
 // takes a band and runs one lane per (particle, band) over the ranges of all e2
 // planes, so its 64 lanes walk rows of the same relative offsets, whose lengths
 // differ by at most a node or two, no row is ever cut by the tile, and the
-// record load and decode of an item serve kBand rows.  Records are read straight
+// record load and decode of an item serve KB rows.  Records are read straight
 // from the cell-sorted array (L2) through a buffer resource, one item ahead of
 // use, so the loads overlap the previous item's LDS atomics (they wait on a
 // different counter).  Per row, the weight of the first node is one exp2; the
@@ -557,8 +557,9 @@ __device__ __forceinline__ uint32_t fixed32(float v) {
 // Integer additions commute, so the forcing does not depend on the order of the
 // adds.
 // TZ: the plan's pencil depth rounded up to a power of two (>= every box's T2);
-// a row class has at most 2 TZ record ranges.  NT: threads per workgroup.
-template <int TZ, int NT>
+// a row class has at most 2 TZ record ranges.  NT: threads per workgroup.  KB:
+// rows per work item.
+template <int TZ, int NT, int KB>
 __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
                                                            int nbox,
                                                            const int64_t *__restrict__ stepp,
@@ -621,7 +622,7 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
         __syncthreads();
         if (tid < nz) {
             // the rows dy of plane dz that some particle reaches form one interval
-            // (the test is convex in |dy|); it is cut into bands of kBand rows
+            // (the test is convex in |dy|); it is cut into bands of KB rows
             const int dz = mlo2 + tid;
             const float az = (float)(dz >= 1 ? dz - 1 : -dz) * B.dxf[2];
             int lo = 1 << 20, hi = -(1 << 20);
@@ -633,8 +634,8 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
                     hi = max(hi, dy);
                 }
             }
-            for (int dy0 = lo; dy0 <= hi; dy0 += kBand) {
-                const int nb = min(kBand, hi - dy0 + 1);
+            for (int dy0 = lo; dy0 <= hi; dy0 += KB) {
+                const int nb = min(KB, hi - dy0 + 1);
                 s_cls[atomicAdd(&s_ncls, 1)] = (dz + 64) | ((dy0 + 64) << 8) | (nb << 16);
             }
         }
@@ -752,7 +753,7 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
                 const float ra = __builtin_amdgcn_exp2f(chx2 * fmaf(2.0f, qa.x, -1.0f));
                 const float sax = qb.x * scale, say = qb.y * scale, saz = qb.z * scale;
 #pragma unroll
-                for (int r = 0; r < kBand; ++r) {
+                for (int r = 0; r < KB; ++r) {
                     if (r >= nb) break;
                     const int y = y0 + r;
                     if (y < 0 || y >= e1) continue;
@@ -1164,15 +1165,40 @@ hipError_t fast_prepare_bound_lds(size_t bytes) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// The scatter instance of a plan: pencil depth TZ (rounded up to a power of
+// two), workgroup size and rows per work item.
+using ScatterFn = void (*)(const DevBox *, int, const int64_t *, int, const int32_t *,
+                           const float4 *, const float *, int64_t, int64_t);
+
+template <int NT, int KB>
+ScatterFn scatter_fn_tz(int tz) {
+    return tz <= 1   ? k_scatter<1, NT, KB>
+         : tz <= 2 ? k_scatter<2, NT, KB>
+         : tz <= 4 ? k_scatter<4, NT, KB>
+                   : k_scatter<8, NT, KB>;
+}
+
+template <int NT>
+ScatterFn scatter_fn_nt(int tz, int band) {
+    static_assert(kMinBand == 2 && kMaxBand == 4, "instances below cover kMinBand..kMaxBand");
+    return band <= 2 ? scatter_fn_tz<NT, 2>(tz)
+         : band == 3 ? scatter_fn_tz<NT, 3>(tz)
+                     : scatter_fn_tz<NT, 4>(tz);
+}
+
+ScatterFn scatter_fn(int tz, bool big, int band) {
+    return big ? scatter_fn_nt<1024>(tz, band) : scatter_fn_nt<512>(tz, band);
+}
+
 hipError_t fast_prepare_lds(size_t bytes) {
-    const void *fns[] = {(const void *)k_scatter<1, 512>,  (const void *)k_scatter<2, 512>,
-                         (const void *)k_scatter<4, 512>,  (const void *)k_scatter<8, 512>,
-                         (const void *)k_scatter<1, 1024>, (const void *)k_scatter<2, 1024>,
-                         (const void *)k_scatter<4, 1024>, (const void *)k_scatter<8, 1024>};
-    for (const void *fn : fns) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-    }
+    for (int big = 0; big < 2; ++big)
+        for (int tz = 1; tz <= 8; tz *= 2)
+            for (int band = kMinBand; band <= kMaxBand; ++band) {
+                hipError_t e = hipFuncSetAttribute((const void *)scatter_fn(tz, big != 0, band),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   (int)bytes);
+                if (e != hipSuccess) return e;
+            }
     return hipSuccess;
 }
 
@@ -1194,16 +1220,8 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
             break;
         case 3:
             {
-                const int tz = P->tile[2];
                 const bool big = P->tile[0] == 1024;
-                auto fn = big ? (tz <= 1   ? k_scatter<1, 1024>
-                                 : tz <= 2 ? k_scatter<2, 1024>
-                                 : tz <= 4 ? k_scatter<4, 1024>
-                                           : k_scatter<8, 1024>)
-                              : (tz <= 1   ? k_scatter<1, 512>
-                                 : tz <= 2 ? k_scatter<2, 512>
-                                 : tz <= 4 ? k_scatter<4, 512>
-                                           : k_scatter<8, 512>);
+                const ScatterFn fn = scatter_fn(P->tile[2], big, P->band);
                 hipLaunchKernelGGL(k_block_sums, dim3((unsigned)P->bblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step + 1, P->M, P->s.start, P->s.rec,
                                    P->s.bsum);

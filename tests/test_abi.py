@@ -154,6 +154,9 @@ def test_setters_reject_a_null_plan():
     assert lib.erpp_plan_set_faxen(None, 0, C.c_double(0.1)) == erpp.ERPP_EINVAL
     assert lib.erpp_plan_set_integrator(None, 0) == erpp.ERPP_EINVAL
     assert lib.erpp_plan_set_added_mass(None, 0, C.c_double(0.1), None) == erpp.ERPP_EINVAL
+    assert lib.erpp_plan_set_rows_per_item(None, 3) == erpp.ERPP_EINVAL
+    rows = C.c_int32(0)
+    assert lib.erpp_plan_get_rows_per_item(None, C.byref(rows)) == erpp.ERPP_EINVAL
     assert lib.erpp_last_error()
 
 

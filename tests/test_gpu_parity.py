@@ -358,13 +358,57 @@ def test_tuner_leaves_the_state_of_the_run():
         plan.run(w.M + 1, 3, graph=False)
         torch.cuda.synchronize()
         a = (db.x.cpu().numpy(), db.v.cpu().numpy(), db.f.cpu().numpy())
+        rows = plan.get_rows_per_item()
+        assert 2 <= rows <= 4
     db2 = upload(box, w.M, erpp.F32_FAST)
     with erpp.Plan([db2], w.M, w.dt) as plan2:
         plan2.set_tile(tile)
+        plan2.set_rows_per_item(rows)
         plan2.run(0, w.M + 4, graph=False)
         torch.cuda.synchronize()
         b = (db2.x.cpu().numpy(), db2.v.cpu().numpy(), db2.f.cpu().numpy())
     for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+def test_rows_per_item_leaves_the_forcing_unchanged():
+    """The scatter's rows per work item change only how the rows are dealt to the
+    lanes: with exact integer accumulation the forcing, and so the whole run, is
+    bit-identical for 2, 3 and 4 rows per item, eager and under graph replay
+    (a change after a capture takes effect on the next replay), and the plan
+    rejects other values."""
+    _cuda()
+    w = workloads.config(3, np_=30000, n=(64, 32, 32), L=(math.pi, math.pi / 2, math.pi / 2),
+                         n_blobs=50)
+    box = workloads.make_boxes(w)[0]
+    outs = {}
+    for rows in (2, 3, 4):
+        db = upload(box, w.M, erpp.F32_FAST)
+        with erpp.Plan([db], w.M, w.dt) as plan:
+            assert plan.get_rows_per_item() == 3
+            plan.set_rows_per_item(rows)
+            assert plan.get_rows_per_item() == rows
+            plan.run(0, w.M + 3, graph=False)
+            torch.cuda.synchronize()
+            outs[rows] = (db.x.cpu().numpy(), db.v.cpu().numpy(), db.f.cpu().numpy())
+            for bad in (0, 1, 5):
+                with pytest.raises(erpp.ErppError) as e:
+                    plan.set_rows_per_item(bad)
+                assert e.value.status == erpp.ERPP_EINVAL
+            assert plan.get_rows_per_item() == rows
+    for rows in (2, 4):
+        for u, v in zip(outs[3], outs[rows]):
+            assert np.array_equal(u, v), rows
+    assert np.any(outs[3][2] != 0.0)
+    db = upload(box, w.M, erpp.F32_FAST)
+    with erpp.Plan([db], w.M, w.dt) as plan:
+        plan.set_rows_per_item(2)
+        plan.run(0, w.M + 1, graph=True)
+        plan.set_rows_per_item(4)
+        plan.run(w.M + 1, 2, graph=True)
+        torch.cuda.synchronize()
+        g = (db.x.cpu().numpy(), db.v.cpu().numpy(), db.f.cpu().numpy())
+    for u, v in zip(outs[3], g):
         assert np.array_equal(u, v)
 
 
