@@ -112,9 +112,9 @@ def kernel_source_hash():
 
 
 def traffic_from_profiles(stage, workload):
-    """HBM bytes per launch of a stage's kernels from the committed rocprofv3
-    counter summary, when it was taken on the current kernel source and on this
-    workload; else None."""
+    """HBM bytes per launch of a stage's kernels (stage None: of the whole step)
+    from the committed rocprofv3 counter summary, when it was taken on the
+    current kernel source and on this workload; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -126,7 +126,7 @@ def traffic_from_profiles(stage, workload):
         return None
     total, found = 0.0, False
     for name, ent in data.get("kernels", {}).items():
-        if name.split("<")[0] in STAGE_KERNELS[stage]:
+        if stage is None or name.split("<")[0] in STAGE_KERNELS[stage]:
             total += ent.get("bytes_per_launch", 0.0)
             found = True
     return round(total) if found else None
@@ -196,10 +196,16 @@ def measure_fast(boxes, w, K, W, args, erpp, torch, tile=None, stage_steps=10):
             "lds_atomic_tops": round(lds_ops / (stage_ms[dom] * 1e-3) / 1e12, 3),
             "lds_peak_tops": round(LDS_PEAK_TOPS, 2)}
     step_gbs = step_bytes / (ms_step * 1e-3) / 1e9
+    # the same step's HBM bytes as the counters measured them (FETCH_SIZE +
+    # WRITE_SIZE of every kernel, profiles/traffic.json), when they apply
+    counted = traffic_from_profiles(None, w.name)
+    counted_frac = (round(counted / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                    if counted else None)
     res = {"value": value, "ms_per_step": ms_step, "tile": list(tile),
            "rows_per_item": plan.get_rows_per_item(), "prefill": prefill,
            "warmup": W, "steps": K, "steps_done": steps_done,
            "hbm_frac_step": round(step_gbs / HBM_PEAK_GBS, 4),
+           "hbm_frac_step_counted": counted_frac,
            "algorithmic_bytes_per_step": step_bytes,
            "stage_us": {n: round(t * 1e3, 2) for n, t in zip(STAGES_FAST, stage_ms)},
            "roofline": roof}
@@ -346,6 +352,7 @@ def main():
                    "integration": "f64",
                    "prefill_steps": res["prefill"]},
         "hbm_frac_step": res["hbm_frac_step"],
+        "hbm_frac_step_counted": res["hbm_frac_step_counted"],
         "algorithmic_bytes_per_step": res["algorithmic_bytes_per_step"],
         "stage_us": res["stage_us"],
         "roofline": res["roofline"],
