@@ -82,7 +82,6 @@ void free_scratch(erpp_plan *p) {
     (void)hipFree(s.pscale);
     (void)hipFree(s.xs);
     (void)hipFree(s.part);
-    (void)hipFree(s.ticket);
     (void)hipFree(s.pamp);
     (void)hipFree(s.pphi);
     (void)hipFree(s.pbase);
@@ -132,9 +131,8 @@ erpp_status alloc_bins(erpp_plan *p) {
     const size_t nc = (size_t)std::max<int64_t>(p->ncell_total, 1);
     const size_t nchunk = (nc + erpp::kScanChunk - 1) / erpp::kScanChunk;
     if (alloc(&p->s.count, nc) != hipSuccess || alloc(&p->s.start, nc + 1) != hipSuccess ||
-        alloc(&p->s.part, nchunk + 1) != hipSuccess || alloc(&p->s.ticket, 1) != hipSuccess)
+        alloc(&p->s.part, nchunk + 1) != hipSuccess)
         return fail(ERPP_ENOMEM, "cell arrays (%lld cells)", (long long)p->ncell_total);
-    HIP_OR_RETURN(hipMemset(p->s.ticket, 0, sizeof(int32_t)));
     HIP_OR_RETURN(hipMemset(p->s.count, 0, sizeof(int32_t) * nc));
     HIP_OR_RETURN(hipMemset(p->s.start, 0, sizeof(int32_t) * (nc + 1)));
     return ERPP_OK;

@@ -88,7 +88,6 @@ struct Scratch {
     int32_t *count = nullptr;    // [ncell_total]   per-step cell histogram (kept zero at rest)
     int32_t *start = nullptr;    // [ncell_total+1] exclusive scan of count
     int32_t *part = nullptr;     // [nchunk+1]      scan partials
-    int32_t *ticket = nullptr;   // [1]             scan: workgroups done (zero at rest)
     int32_t *rank = nullptr;     // [np_total]      rank of a particle inside its cell
     float4 *rec = nullptr;       // [2*np_total]    cell-sorted injection records
     float *bsum = nullptr;       // [nkey_total]    max_c |amplitude| summed over x-blocks X-1..X+1
@@ -168,11 +167,11 @@ hipError_t fast_gather(erpp_plan *p, double *u_p, hipStream_t st);
 hipError_t fast_bin_positions(erpp_plan *p, int ibox, const double *pos, int32_t *key,
                               int32_t *perm, int32_t *bin_start, hipStream_t st);
 // exact cell binning with caller-provided scratch: count [ncell] (zero on entry
-// unless clear), rank [np], part [ncell / kScanChunk + 2], ticket [1] (zero on
-// entry unless clear); count and ticket are zero again on exit
+// unless clear), rank [np], part [ncell / kScanChunk + 2]; count is zero again on
+// exit
 hipError_t bin_positions(const BinGeom &G, const double *pos, int32_t *key, int32_t *perm,
                          int32_t *bin_start, int32_t *count, int32_t *rank, int32_t *part,
-                         int32_t *ticket, bool clear, hipStream_t st);
+                         bool clear, hipStream_t st);
 hipError_t plain_scatter_stages(erpp_plan *p, hipStream_t st);
 hipError_t plain_update_stage(erpp_plan *p, hipStream_t st);
 hipError_t set_step(erpp_plan *p, int64_t n, hipStream_t st);
@@ -182,8 +181,8 @@ hipError_t mark_memory_terms(erpp_plan *p, hipStream_t st);
 bool fill_box_tiles(erpp_plan *p);
 erpp_status ensure_aux(erpp_plan *p);   // allocate Scratch::aux / vrec (FP32 path)          // tiles, blocks, LDS layout; false if it does not fit
 // start = exclusive scan of count, count = 0; with stepp, also step[1] = step[0]++
-hipError_t scan_counts(int32_t *count, int64_t n, int32_t *start, int32_t *part, int32_t *ticket,
-                       int64_t *stepp, hipStream_t st);
+hipError_t scan_counts(int32_t *count, int64_t n, int32_t *start, int32_t *part, int64_t *stepp,
+                       hipStream_t st);
 hipError_t fast_prepare_lds(size_t bytes);         // opt the scatter into > 64 KB LDS
 hipError_t fast_prepare_bound_lds(size_t bytes);   // same for the pencil-scale kernel
 constexpr size_t kMaxScatterLds = 150 * 1024;

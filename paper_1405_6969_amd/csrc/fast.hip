@@ -1149,11 +1149,10 @@ __global__ void __launch_bounds__(kBlock) k_fill_zero(int32_t *__restrict__ word
 
 }  // namespace
 
-hipError_t scan_counts(int32_t *count, int64_t n, int32_t *start, int32_t *part, int32_t *ticket,
-                       int64_t *stepp, hipStream_t st) {
+hipError_t scan_counts(int32_t *count, int64_t n, int32_t *start, int32_t *part, int64_t *stepp,
+                       hipStream_t st) {
     const int64_t nchunk = (n + kScanChunk - 1) / kScanChunk;
     if (nchunk == 0) return hipErrorInvalidValue;
-    (void)ticket;
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nchunk), dim3(256), 0, st, count, n, part);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nchunk), dim3(256), 0, st, count, n, part,
                        nchunk, start, stepp);
@@ -1210,7 +1209,7 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                                    P->dbox, P->nbox, P->s.step, P->M, P->s.count, P->s.rank);
             break;
         case 1:
-            return scan_counts(P->s.count, P->nkey_total, P->s.start, P->s.part, P->s.ticket,
+            return scan_counts(P->s.count, P->nkey_total, P->s.start, P->s.part,
                                P->s.step, st);
         case 2:
             if (P->np_total > 0)
@@ -1292,20 +1291,18 @@ hipError_t fast_gather(erpp_plan *P, double *u_p, hipStream_t st) {
 
 hipError_t bin_positions(const BinGeom &G, const double *pos, int32_t *key, int32_t *perm,
                          int32_t *bin_start, int32_t *count, int32_t *rank, int32_t *part,
-                         int32_t *ticket, bool clear, hipStream_t st) {
+                         bool clear, hipStream_t st) {
     const int64_t nc = (int64_t)G.n[0] * G.n[1] * G.n[2];
     const unsigned blocks = (unsigned)((G.np + kBlock - 1) / kBlock);
-    if (clear) {
+    if (clear)
         hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((nc + kBlock - 1) / kBlock)),
                            dim3(kBlock), 0, st, count, nc);
-        hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(kBlock), 0, st, ticket, (int64_t)1);
-    }
     if (G.np > 0)
         hipLaunchKernelGGL(k_bin_pos_count, dim3(blocks), dim3(kBlock), 0, st, G, pos, key, count,
                            rank);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = scan_counts(count, nc, bin_start, part, ticket, nullptr, st);
+    e = scan_counts(count, nc, bin_start, part, nullptr, st);
     if (e != hipSuccess) return e;
     if (G.np > 0)
         hipLaunchKernelGGL(k_bin_pos_place, dim3(blocks), dim3(kBlock), 0, st, G, key, bin_start,
@@ -1324,7 +1321,7 @@ hipError_t fast_bin_positions(erpp_plan *P, int ibox, const double *pos, int32_t
     }
     G.np = H.np;
     return bin_positions(G, pos, key, perm, bin_start, P->s.count + H.cell_off,
-                         P->s.rank + H.poff, P->s.part, P->s.ticket, false, st);
+                         P->s.rank + H.poff, P->s.part, false, st);
 }
 
 }  // namespace erpp

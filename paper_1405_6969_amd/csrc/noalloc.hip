@@ -15,15 +15,14 @@ namespace {
 // Largest box the static scratch holds.
 constexpr int64_t kStaticMaxCells = int64_t(1) << 21;       // e.g. 128^3
 constexpr int64_t kStaticMaxParticles = int64_t(1) << 21;
-// Layout in 32-bit words: ticket, scan partials, histogram, ranks (each region
-// starts on a 256-byte boundary).
-constexpr int64_t kTicketOff = 0;
-constexpr int64_t kPartOff = 64;
+// Layout in 32-bit words: scan partials, histogram, ranks (each region starts on
+// a 256-byte boundary).
+constexpr int64_t kPartOff = 0;
 constexpr int64_t kPartWords = kStaticMaxCells / erpp::kScanChunk + 64;
 constexpr int64_t kCountOff = kPartOff + kPartWords;
 constexpr int64_t kRankOff = kCountOff + kStaticMaxCells;
 constexpr int64_t kScratchWords = kRankOff + kStaticMaxParticles;
-static_assert(kPartOff % 64 == 0 && kCountOff % 64 == 0 && kRankOff % 64 == 0,
+static_assert(kPartWords % 64 == 0 && kCountOff % 64 == 0 && kRankOff % 64 == 0,
               "256-byte aligned regions");
 
 // Device scratch of erpp_bin_static.  In host code `scratch` names a host-side
@@ -90,10 +89,10 @@ extern "C" erpp_status erpp_bin_static(const int32_t n[3], const double L[3], in
     int32_t *base = nullptr;
     erpp_status s = scratch_on_device(&base);
     if (s != ERPP_OK) return s;
-    // the histogram and the scan ticket start from zero on every call (a call
-    // that ended early may have left them dirty)
+    // the histogram starts from zero on every call (a call that ended early may
+    // have left it dirty)
     hipError_t e = erpp::bin_positions(G, pos, key, perm, bin_start, base + kCountOff,
-                                       base + kRankOff, base + kPartOff, base + kTicketOff, true,
+                                       base + kRankOff, base + kPartOff, true,
                                        (hipStream_t)stream);
     if (e != hipSuccess) return erpp::hip_fail(e, "erpp_bin_static launch");
     return ERPP_OK;
