@@ -7,15 +7,18 @@
 //                 publishes the step index for the kernels after it
 //   k_eval        per particle: FP64 cell/offset of X^{n-M}, FP32 Gaussian
 //                 normalisation over the 3-sigma sphere, record
-//                 {offsets, amplitude} written at its cell-sorted slot
+//                 {offsets, amplitude} written at its cell-sorted slot, and x^n
+//                 in record order
+//   k_block_sums, k_pencil_scale  the fixed-point bound of every scatter pencil
 //   k_scatter     one workgroup per pencil of nodes (full x extent): the
 //                 stencil rows of every particle that reaches the pencil are
 //                 accumulated into an LDS copy of it, which is then stored (each
 //                 node written once, no global atomics)
 //   k_gather_sorted  carrier at x^n by trilinear interpolation, particles
-//                 visited in cell order (records of level n - M)
+//                 visited in cell order (records of level n - M), results in
+//                 particle order
 //   k_update      per particle: closed-form self term, Stokes drag, history
-//                 write, explicit Euler, wrap
+//                 write, the step of the chosen integrator, wrap
 #include <hip/hip_runtime.h>
 
 #include "erpp_device.hpp"
