@@ -104,7 +104,7 @@ __device__ __forceinline__ bool inside32(int mx, float phx, float ryz, const Dev
 // the roundings of the sqrt and of phi -/+ s the estimated ends are off by less
 // than gs / s, gs = 2 guard / dx^2 + 1e-6 smax (smax + 1).  When both estimated
 // ends phi -/+ s lie farther than that from every node, ceil and floor of them
-// are the exact ends.  Otherwise (rare: a few 1e-5 of the rows) each end is
+// are the exact ends.  Otherwise (rare: a few rows in 1e4) each end is
 // settled by one exact decision (inside32 semantics) at the node k nearest the
 // estimated end: the end is k if k is inside, else the next node inward; a row
 // with s < 0.01 can hold only the node nearest phi, which both ends then test.
