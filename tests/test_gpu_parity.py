@@ -134,6 +134,55 @@ def test_scatter_fp64_fallback_band():
     assert rel_l2(fg, fo) <= 1e-5
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("sigma_dx", [1.5, 2.0])
+def test_scatter_row_ends_near_nodes(prec, sigma_dx):
+    """Particles whose stencil rows end within 1e-7..1e-4 of a node, on both
+    sides: the row (dy, dz) of a particle at (phi_x, phi_y, phi_z) = (f, d1, d2)
+    (d1, d2 tiny) has half-width s = sqrt(R^2 - dy^2 - dz^2) nodes, and phi_x is
+    put at an integer -/+ s +/- delta.  The fast path must settle these ends
+    exactly (the estimate's own error bound routes them to the exact test), so
+    the set of nodes touched equals the oracle's, node for node, and the
+    forcing meets the node-by-node bar."""
+    _cuda()
+    n = 32
+    L = 2 * math.pi
+    dx = L / n
+    R = 3.0 * sigma_dx
+    rng = np.random.default_rng(11)
+    pos = []
+    for dy, dz in [(0, 0), (1, 0), (2, 1), (3, 2), (0, 4), (4, 1)]:
+        r2 = R * R - dy * dy - dz * dz
+        if r2 <= 0:
+            continue
+        sh = math.sqrt(r2)
+        for delta in (-1e-4, -3e-6, -1e-7, 1e-7, 3e-6, 1e-4):
+            for side in (-1, 1):
+                # left end phi - s or right end phi + s at an integer, plus delta
+                f = (math.ceil(sh) - sh if side < 0 else sh - math.floor(sh)) + delta
+                f = f % 1.0
+                pos.append((f, rng.uniform(-2e-7, 2e-7) % 1.0, rng.uniform(-2e-7, 2e-7) % 1.0))
+    npart = len(pos)
+    cells = rng.choice(n ** 3, size=npart, replace=False)
+    X = np.empty((3, npart))
+    for p_, (c, (fx, fy, fz)) in enumerate(zip(cells, pos)):
+        i, j, k = c % n, (c // n) % n, c // (n * n)
+        X[:, p_] = ((i + fx) * dx, (j + fy) * dx, (k + fz) * dx)
+    box = workloads.tiny_box(13, n=(n, n, n), np_=npart, L=(L, L, L), sigma_dx=sigma_dx)
+    box.x = X
+    M = 2
+    D = rng.normal(size=(3, npart)).astype(np.float32).astype(np.float64)
+    db = upload(box, M, prec)
+    _fill_level(db, (5 - M) % (M + 1), X, D)
+    with erpp.Plan([db], M, 1e-3, precision=prec) as plan:
+        plan.scatter(5)
+        fg = db.f.double().cpu().numpy()
+    P = oracle.params_for_box(box, M, 1e-3)
+    fo = oracle.deposit(P, X, D)
+    assert np.array_equal(fg != 0, fo != 0)
+    assert_forcing_matches(fg, fo, prec, "row ends near nodes")
+
+
 # --------------------------------------------------------------- gather ----
 
 @pytest.mark.parametrize("prec", PRECS)
