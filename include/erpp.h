@@ -219,7 +219,9 @@ erpp_status erpp_plan_set_basset(erpp_plan *plan, int32_t ibox, double a, double
 erpp_status erpp_plan_set_integrator(erpp_plan *plan, erpp_integrator kind);
 
 /* Autotuner (ERPP_F32_FAST): times every candidate pencil shape on the plan's own
- * boxes with the scatter of step n, the step following the last one run (the
+ * boxes (a fixed table plus the balanced heights of the tallest box: its y extent
+ * split into the fewest equal pencils that fit the LDS, and into one more) with
+ * the scatter of step n, the step following the last one run (the
  * ring, positions and velocities are only read) and keeps the fastest; then, at
  * that pencil, the rows per work item (erpp_plan_set_rows_per_item).
  * Afterwards the step counter is n again and every box's f holds the forcing of

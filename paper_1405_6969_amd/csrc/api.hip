@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -773,11 +774,34 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
             }
         }
     }
-    static const int32_t cand[][3] = {{512, 16, 1},  {512, 8, 2},   {512, 8, 1},  {512, 4, 4},
-                                      {512, 4, 2},   {512, 32, 1},  {512, 2, 2},  {512, 4, 1},
-                                      {1024, 32, 1}, {1024, 16, 2}, {1024, 16, 1}, {1024, 8, 4},
-                                      {1024, 64, 1}, {1024, 8, 2}};
-    const int ncand = (int)(sizeof cand / sizeof cand[0]);
+    static const int32_t fixed[][3] = {{512, 16, 1},  {512, 8, 2},   {512, 8, 1},  {512, 4, 4},
+                                       {512, 4, 2},   {512, 32, 1},  {512, 2, 2},  {512, 4, 1},
+                                       {1024, 32, 1}, {1024, 16, 2}, {1024, 16, 1}, {1024, 8, 4},
+                                       {1024, 64, 1}, {1024, 8, 2}};
+    std::vector<std::array<int32_t, 3>> cand;
+    for (const auto &c : fixed) cand.push_back({c[0], c[1], c[2]});
+    // balanced heights: the fewest pencils per y extent of the tallest box whose
+    // equal split fits the LDS, and one more (a plane of Ny rows in k pencils of
+    // ceil(Ny / k) rows rather than full pencils and a short last one)
+    {
+        int32_t ny = 1;
+        for (const auto &B : p->hbox) ny = std::max(ny, B.n[1]);
+        const int32_t keep[3] = {p->tile[0], p->tile[1], p->tile[2]};
+        int found = 0;
+        for (int32_t k = 1; k <= ny && found < 2; ++k) {
+            const int32_t t1 = (ny + k - 1) / k;
+            if (t1 > erpp::kMaxTileY) continue;
+            const int32_t c[3] = {1024, t1, 1};
+            if (found == 0 && erpp_plan_set_tile(p, c) != ERPP_OK) continue;
+            bool dup = false;
+            for (const auto &d : cand) dup |= d[0] == c[0] && d[1] == c[1] && d[2] == c[2];
+            if (!dup) cand.push_back({c[0], c[1], c[2]});
+            ++found;
+        }
+        const erpp_status s = erpp_plan_set_tile(p, keep);
+        if (s != ERPP_OK) return s;
+    }
+    const int ncand = (int)cand.size();
     int32_t best[3] = {p->tile[0], p->tile[1], p->tile[2]};
     float best_ms = 1e30f;
     hipEvent_t a, b;
@@ -815,13 +839,13 @@ erpp_status erpp_plan_tune(erpp_plan *p, const char *cache_path, void *stream) {
     int32_t best_rows = erpp::kDefaultBand;
     if (p->band != best_rows) status = erpp_plan_set_rows_per_item(p, best_rows);
     for (int c = 0; c < ncand && status == ERPP_OK; ++c) {
-        if (check_tile(cand[c]) != ERPP_OK) continue;
-        if (erpp_plan_set_tile(p, cand[c]) != ERPP_OK) continue;   // does not fit these boxes
+        if (check_tile(cand[c].data()) != ERPP_OK) continue;
+        if (erpp_plan_set_tile(p, cand[c].data()) != ERPP_OK) continue;   // does not fit these boxes
         float ms = 0.f;
         time_scatter(ms);
         if (status == ERPP_OK && ms < best_ms) {
             best_ms = ms;
-            std::memcpy(best, cand[c], sizeof best);
+            std::memcpy(best, cand[c].data(), sizeof best);
         }
     }
     if (status == ERPP_OK) status = erpp_plan_set_tile(p, best);

@@ -826,34 +826,43 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
     }
     __syncthreads();
     // store: node x of a pencil row = index x - mlo plus its periodic images
-    // x + Nx - mlo (for x < mhi) and x - Nx - mlo (for x >= Nx + mlo)
+    // x + Nx - mlo (for x < mhi) and x - Nx - mlo (for x >= Nx + mlo).  Each wave
+    // stores whole pencil rows, lanes along x, so the row and its place in the
+    // box are wave-uniform and no lane divides
     float *f = (float *)B.f;
     const float inv = 1.0f / scale;
     const int64_t ng = (int64_t)Nx * Ny * Nz;
-    const int cnt = Nx * e1 * e2;
-    for (int i = tid; i < cnt; i += NT) {
-        const int x = i % Nx;
-        const int r = i / Nx;
-        const int ly = r % e1, lz = r / e1;
-        const int64_t g = ((int64_t)(o2 + lz) * Ny + (o1 + ly)) * Nx + x;
-        const int base = 3 * ((lz * T1 + ly) * PXa);
-        const int a = base + 3 * (x - mlo0);
-        int v0 = acc[a], v1 = acc[a + 1], v2 = acc[a + 2];
-        if (x < mhi0) {
-            const int a2 = a + 3 * Nx;
-            v0 += acc[a2];
-            v1 += acc[a2 + 1];
-            v2 += acc[a2 + 2];
+    const int nw = NT >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    int ly = wv % e1, lz = wv / e1;
+    for (int r = wv; r < e1 * e2; r += nw) {
+        float *fr = f + ((int64_t)(o2 + lz) * Ny + (o1 + ly)) * Nx;
+        const int base = 3 * ((lz * T1 + ly) * PXa - mlo0);
+        for (int x = lane; x < Nx; x += 64) {
+            const int a = base + 3 * x;
+            int v0 = acc[a], v1 = acc[a + 1], v2 = acc[a + 2];
+            if (x < mhi0) {
+                const int a2 = a + 3 * Nx;
+                v0 += acc[a2];
+                v1 += acc[a2 + 1];
+                v2 += acc[a2 + 2];
+            }
+            if (x >= Nx + mlo0) {
+                const int a2 = a - 3 * Nx;
+                v0 += acc[a2];
+                v1 += acc[a2 + 1];
+                v2 += acc[a2 + 2];
+            }
+            fr[x] = (float)v0 * inv;
+            fr[ng + x] = (float)v1 * inv;
+            fr[2 * ng + x] = (float)v2 * inv;
         }
-        if (x >= Nx + mlo0) {
-            const int a2 = a - 3 * Nx;
-            v0 += acc[a2];
-            v1 += acc[a2 + 1];
-            v2 += acc[a2 + 2];
+        // next row of this wave: r + nw = (lz, ly) advanced by nw rows of e1
+        ly += nw;
+        while (ly >= e1) {
+            ly -= e1;
+            ++lz;
         }
-        f[g] = (float)v0 * inv;
-        f[ng + g] = (float)v1 * inv;
-        f[2 * ng + g] = (float)v2 * inv;
     }
 }
 
