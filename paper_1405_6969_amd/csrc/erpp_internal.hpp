@@ -178,8 +178,8 @@ hipError_t set_step(erpp_plan *p, int64_t n, hipStream_t st);
 hipError_t advance_step(erpp_plan *p, hipStream_t st);
 // after an update: the added-mass and Basset histories of the boxes using them exist
 hipError_t mark_memory_terms(erpp_plan *p, hipStream_t st);
-bool fill_box_tiles(erpp_plan *p);
-erpp_status ensure_aux(erpp_plan *p);   // allocate Scratch::aux / vrec (FP32 path)          // tiles, blocks, LDS layout; false if it does not fit
+bool fill_box_tiles(erpp_plan *p);      // tiles, blocks, LDS layout; false if it does not fit
+erpp_status ensure_aux(erpp_plan *p);   // allocate Scratch::aux / vrec (FP32 path)
 // start = exclusive scan of count, count = 0; with stepp, also step[1] = step[0]++
 hipError_t scan_counts(int32_t *count, int64_t n, int32_t *start, int32_t *part, int64_t *stepp,
                        hipStream_t st);
