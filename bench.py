@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--rows-per-item", type=int, default=0, metavar="R",
                     help="stencil rows per work item of the scatter (2..4; default: the "
                          "autotuner's choice, or 3 with --tile / --no-tune)")
+    ap.add_argument("--no-stream-copy", action="store_true",
+                    help="skip the device-copy bandwidth measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (the reference kernel "
                          "for scaling HBM counter readings)")
@@ -337,6 +339,9 @@ def main():
         torch.cuda.empty_cache()
         variants = bench_variants(boxes[0], w, tile, min(K, 100), erpp, torch)
         log(f"[bench] variants {variants}")
+    copy_bw = None if args.no_stream_copy else stream_copy(torch)
+    if copy_bw:
+        log(f"[bench] stream copy {copy_bw}")
     if args.copy_calibration > 0:
         nel = args.copy_calibration * (1 << 20) // 4
         src = torch.ones(nel, dtype=torch.float32, device="cuda")
@@ -368,8 +373,35 @@ def main():
         "cpu_baseline": cpu,
         "coupled": coupled,
         "variants": variants,
+        "stream_copy": copy_bw,
     }
     print(json.dumps(out), flush=True)
+
+
+def stream_copy(torch, mib=512, reps=20):
+    """Achievable HBM rate beside the published 8 TB/s: a plain device-to-device copy of
+    `mib` MiB (read + written), timed with events on torch's current stream, where the
+    copy runs."""
+    nel = mib * (1 << 20) // 4
+    src = torch.ones(nel, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    nbytes = 2 * nel * 4
+    return {"mib": mib, "bytes_per_copy": nbytes, "us": round(ms * 1e3, 2),
+            "gbs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+            "frac_of_peak": round(nbytes / (ms * 1e-3) / 8e12, 4)}
 
 
 def bench_coupled(box, w, tile, K, erpp, torch):
