@@ -48,6 +48,10 @@ def _fill_level(db, slot, X, D):
     # through the periodic wrap, of blocks 2 and 3; blobs straddle x = 0
     ((50, 40, 36), 2400, 1.5, (1024, 32, 1), "wrap_x"),
     ((66, 20, 20), 1200, 1.5, (0, 8, 2), "wrap_x"),          # a 2-cell last block, 5 blocks
+    # store by whole rows per wave: an odd height whose last pencil has one row, and
+    # pencils of 5 planes (the 8-plane instance) ragged in y and in z
+    ((64, 40, 24), 3000, 1.5, (1024, 13, 1), "clustered"),
+    ((40, 36, 44), 2500, 1.5, (1024, 7, 5), "clustered"),
 ])
 def test_scatter_matches_oracle(prec, shape, np_, sigma_dx, tile, placement):
     _cuda()
