@@ -16,6 +16,7 @@ particle sample and a node window, and the oracle itself timed on the host.
 from __future__ import annotations
 
 import argparse
+import glob
 import hashlib
 import json
 import math
@@ -121,16 +122,19 @@ def kernel_source_hash():
 
 def traffic_from_profiles(stage, workload):
     """HBM bytes per launch of a stage's kernels (stage None: of the whole step)
-    from the committed rocprofv3 counter summary, when it was taken on the
-    current kernel source and on this workload; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
-        return None
-    try:
-        data = json.load(open(path))
-    except Exception:
-        return None
-    if data.get("kernel_sha") != kernel_source_hash() or data.get("workload") != workload:
+    from a committed rocprofv3 counter summary (profiles/traffic*.json) taken on
+    the current kernel source and on this workload; else None."""
+    data = None
+    sha = kernel_source_hash()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic*.json"))):
+        try:
+            d = json.load(open(path))
+        except Exception:
+            continue
+        if d.get("kernel_sha") == sha and d.get("workload") == workload:
+            data = d
+            break
+    if data is None:
         return None
     total, found = 0.0, False
     for name, ent in data.get("kernels", {}).items():
@@ -319,6 +323,7 @@ def main():
                   "warmup": W, "prefill_steps": tres["prefill"], "tile": tres["tile"],
                   "rows_per_item": tres["rows_per_item"],
                   "hbm_frac_step": tres["hbm_frac_step"],
+                  "hbm_frac_step_counted": tres["hbm_frac_step_counted"],
                   "algorithmic_bytes_per_step": tres["algorithmic_bytes_per_step"],
                   "stage_us": tres["stage_us"], "roofline": tres["roofline"],
                   "fp64_plain": tplain, "accuracy": tacc}

@@ -365,15 +365,20 @@ static_assert(kBlock % kBoundXChunk == 0 && (kBoundXChunk & (kBoundXChunk - 1)) 
 __global__ void __launch_bounds__(kBlock) k_pencil_scale(const DevBox *__restrict__ Bs, int nbox,
                                                          const int64_t *__restrict__ stepp, int M,
                                                          const float *__restrict__ bsum,
-                                                         float *__restrict__ pscale) {
+                                                         float *__restrict__ pscale,
+                                                         int64_t npen) {
     if (*stepp < M) return;
+    // each XCD (its own L2) takes one contiguous run of pencils, whose windows of
+    // block sums overlap
+    const int64_t pen = xcd_block(blockIdx.x, gridDim.x);
+    if (pen >= npen) return;
     extern __shared__ float win[];              // [WZ][WY][kBoundXChunk] of bsum
     __shared__ int s_off[256];                  // window row offset of each class
     __shared__ int s_wcnt[kBlock / 64];
     __shared__ float s_max[kBlock / 64];
-    const int bi = box_of_block(Bs, nbox, blockIdx.x, [](const DevBox &b) { return b.blk_t; });
+    const int bi = box_of_block(Bs, nbox, pen, [](const DevBox &b) { return b.blk_t; });
     const DevBox &B = Bs[bi];
-    const int t = (int)(blockIdx.x - B.blk_t);
+    const int t = (int)(pen - B.blk_t);
     const int T1 = B.T[1], T2 = B.T[2];
     const int o1 = (t % B.ntile[1]) * T1;
     const int o2 = (t / B.ntile[1]) * T2;
@@ -495,7 +500,7 @@ __global__ void __launch_bounds__(kBlock) k_pencil_scale(const DevBox *__restric
         float bound = 0.0f;
         for (int w = 0; w < kBlock / 64; ++w) bound = fmaxf(bound, s_max[w]);
         bound *= 1.0001f;   // margin for the FP32 roundings of the sums
-        pscale[blockIdx.x] = (bound > 0.0f && bound < 3.0e38f) ? 1073741824.0f / bound : 1.0f;
+        pscale[pen] = (bound > 0.0f && bound < 3.0e38f) ? 1073741824.0f / bound : 1.0f;
     }
 }
 
@@ -1237,9 +1242,9 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                                    P->dbox, P->nbox, P->s.step + 1, P->M, P->s.start, P->s.rec,
                                    P->s.bsum);
                 const int64_t pgrid = (P->tblocks + kXcds - 1) / kXcds * kXcds;
-                hipLaunchKernelGGL(k_pencil_scale, dim3((unsigned)P->tblocks), dim3(kBlock),
+                hipLaunchKernelGGL(k_pencil_scale, dim3((unsigned)pgrid), dim3(kBlock),
                                    P->bound_lds, st, P->dbox, P->nbox, P->s.step + 1, P->M,
-                                   P->s.bsum, P->s.pscale);
+                                   P->s.bsum, P->s.pscale, P->tblocks);
                 hipLaunchKernelGGL(fn, dim3((unsigned)pgrid), dim3(big ? 1024 : 512),
                                    P->lds_bytes, st, P->dbox, P->nbox, P->s.step + 1, P->M,
                                    P->s.start, P->s.rec, P->s.pscale, P->tblocks,
