@@ -174,7 +174,10 @@ __global__ void __launch_bounds__(256) k_scan_down(int32_t *__restrict__ count, 
 // ------------------------------------------------------------------ eval ----
 constexpr int kMaxOff = 16;   // max stencil offsets per dimension (mhi - mlo + 1)
 
-__global__ void __launch_bounds__(kBlock) k_eval(const DevBox *__restrict__ Bs, int nbox,
+// six workgroups per CU: at most 80 VGPRs (66 used), 6 waves per SIMD to hide the
+// latencies of the row loop (exp, sqrt, LDS), which at 5 waves showed as 23% idle
+// VALU issue (53.0 -> 46.2 us on the shear box)
+__global__ void __launch_bounds__(kBlock, 6) k_eval(const DevBox *__restrict__ Bs, int nbox,
                                                  const int64_t *__restrict__ stepp, int M,
                                                  const int32_t *__restrict__ start,
                                                  const int32_t *__restrict__ rank,
