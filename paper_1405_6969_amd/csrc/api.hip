@@ -81,6 +81,7 @@ void free_scratch(erpp_plan *p) {
     (void)hipFree(s.up);
     (void)hipFree(s.bsum);
     (void)hipFree(s.pscale);
+    (void)hipFree(s.pctr);
     (void)hipFree(s.xs);
     (void)hipFree(s.part);
     (void)hipFree(s.pamp);
@@ -408,6 +409,7 @@ erpp_status erpp_plan_create(erpp_plan **out, const erpp_box *boxes, int32_t nbo
         ok = alloc(&p->s.rec, 2 * (size_t)np_total) == hipSuccess &&
              alloc(&p->s.bsum, (size_t)std::max<int64_t>(p->nkey_total, 1)) == hipSuccess &&
              alloc(&p->s.pscale, (size_t)std::max<int64_t>(p->nrows_total, 1)) == hipSuccess &&
+             alloc(&p->s.pctr, 8) == hipSuccess &&
              alloc(&p->s.up, (size_t)np_total) == hipSuccess &&
              alloc(&p->s.xs, (size_t)np_total) == hipSuccess;
     if (ok && prec == ERPP_F64_PLAIN)

@@ -92,6 +92,8 @@ struct Scratch {
     float4 *rec = nullptr;       // [2*np_total]    cell-sorted injection records
     float *bsum = nullptr;       // [nkey_total]    max_c |amplitude| summed over x-blocks X-1..X+1
     float *pscale = nullptr;     // [sum Ny Nz]     fixed-point scale of each scatter pencil
+    int32_t *pctr = nullptr;     // [8]             scatter: pencils handed out of each XCD's
+                                 //                 run (cleared by the pencil-scale kernel)
     double4 *xs = nullptr;       // [np_total]      x^n in record order, particle index in w
     double4 *up = nullptr;       // [np_total]      carrier at x^n in particle order (FP64)
     // grid terms of the optional forces, in particle order (allocated when a box
@@ -136,6 +138,11 @@ struct erpp_plan {
     size_t lds_bytes = 0;
     int32_t band = erpp::kDefaultBand;  // scatter: stencil rows per work item (lane)
     size_t bound_lds = 0;        // dynamic LDS of the pencil-scale kernel
+    // scatter: resident workgroups (compute units x workgroups per unit) of the
+    // instance and LDS size they were computed for
+    int64_t sgrid = 0;
+    const void *sgrid_fn = nullptr;
+    size_t sgrid_lds = 0;
     // graph of one step (step index read from s.step)
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;

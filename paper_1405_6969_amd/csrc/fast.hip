@@ -10,16 +10,19 @@
 //                 {offsets, amplitude} written at its cell-sorted slot, and x^n
 //                 in record order
 //   k_block_sums, k_pencil_scale  the fixed-point bound of every scatter pencil
-//   k_scatter     one workgroup per pencil of nodes (full x extent): the
-//                 stencil rows of every particle that reaches the pencil are
-//                 accumulated into an LDS copy of it, which is then stored (each
-//                 node written once, no global atomics)
+//   k_scatter     pencils of nodes (full x extent), one per workgroup or, on
+//                 large grids, taken in turn by resident workgroups: the stencil
+//                 rows of every particle that reaches the pencil are accumulated
+//                 into an LDS copy of it, which is then stored (each node written
+//                 once, no global atomics)
 //   k_gather_sorted  carrier at x^n by trilinear interpolation, particles
 //                 visited in cell order (records of level n - M), results in
 //                 particle order
 //   k_update      per particle: closed-form self term, Stokes drag, history
 //                 write, the step of the chosen integrator, wrap
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "erpp_device.hpp"
 #include "erpp_internal.hpp"
@@ -32,6 +35,10 @@ namespace {
 // physical block b runs on XCD b mod kXcds; XCD x takes logical blocks
 // [x G/kXcds, (x + 1) G/kXcds).  A bijection on [0, grid).
 constexpr int kXcds = 8;
+// the scatter runs resident workgroups when its pencils exceed this many per
+// resident workgroup (the 512^3 box: 46 per CU, 5.21 -> 4.76 ms per step; at two
+// per CU, as on the 256 x 128 x 128 box, one workgroup per pencil is as fast)
+constexpr int64_t kPersist = 4;
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t grid) {
     return (b % kXcds) * (grid / kXcds) + b / kXcds;
 }
@@ -369,7 +376,9 @@ __global__ void __launch_bounds__(kBlock) k_pencil_scale(const DevBox *__restric
                                                          const int64_t *__restrict__ stepp, int M,
                                                          const float *__restrict__ bsum,
                                                          float *__restrict__ pscale,
-                                                         int64_t npen) {
+                                                         int64_t npen, int32_t *__restrict__ pctr) {
+    // the scatter that follows hands its pencils out from these counters
+    if (blockIdx.x == 0 && threadIdx.x < kXcds) pctr[threadIdx.x] = 0;
     if (*stepp < M) return;
     // each XCD (its own L2) takes one contiguous run of pencils, whose windows of
     // block sums overlap
@@ -537,9 +546,9 @@ __device__ __forceinline__ uint32_t fixed32(float v) {
 }
 
 
-// One workgroup per pencil of nodes: the whole x extent of the box times
-// T1 x T2 nodes in (y, z).  Owner computes: every node of the pencil is written
-// once, by this workgroup; no global atomics.
+// Pencils of nodes: the whole x extent of the box times T1 x T2 nodes in (y, z),
+// each taken by one workgroup.  Owner computes: every node of the pencil is
+// written once, by that workgroup; no global atomics on the grid.
 //
 // Row classes.  Every stencil row of a particle is a relative offset (dy, dz)
 // from its base cell (b0, b1, b2) -- its class.  For class (dy, dz) the
@@ -578,16 +587,58 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
                                                            const int32_t *__restrict__ start,
                                                            const float4 *__restrict__ rec,
                                                            const float *__restrict__ pscale,
-                                                           int64_t npen, int64_t npart) {
+                                                           int64_t npen, int64_t npart,
+                                                           int32_t *__restrict__ pctr,
+                                                           int run, int lds_words) {
     extern __shared__ int32_t lds[];
     __shared__ int s_cls[256];            // row bands: dz, first dy, rows
     __shared__ int s_ncls;
     __shared__ int s_next;                // next class to hand out
     __shared__ float s_q[32];             // exp2(-2 c hx^2 m), m = mlo .. mhi in x
-    // workgroups are dealt to the 8 XCDs round-robin; give each XCD (its own L2)
-    // one contiguous run of pencils, whose record windows overlap
-    const int64_t pen = xcd_block(blockIdx.x, gridDim.x);
-    if (pen >= npen) return;
+    __shared__ int s_pen;                 // the pencil in hand
+    __shared__ int s_clsbox;              // the box whose bands s_cls, s_q hold
+    const int tid = threadIdx.x, lane = tid & 63;
+    // Workgroups take pencils until none is left.  Workgroups are dealt to the 8
+    // XCDs round-robin, so the pencils are cut into 8 contiguous runs (their
+    // record windows overlap, within one L2) and workgroup w drains run w mod 8
+    // first: its first pencil by its index (the first gridDim/8 pencils of every
+    // run), the rest from the run's counter, then the other runs in turn.  Every
+    // workgroup ends once all runs are drained, whatever XCD it landed on.  With
+    // one workgroup per pencil (gridDim/8 = run) no counter is touched.
+    const int home = (int)(blockIdx.x % kXcds);
+    const int first = (int)(gridDim.x / kXcds);
+    const bool again = first < run;       // a workgroup may take more than one pencil
+    int tries = again ? 0 : kXcds;        // runs found drained (thread 0)
+    auto pencil_of = [&](int r, int i) -> int {
+        const int64_t pn = (int64_t)r * run + first + i;
+        return (first + i < run && pn < npen) ? (int)pn : -1;
+    };
+    auto claim_next = [&]() -> int {      // thread 0: next pencil, npen when none
+        while (tries < kXcds) {
+            const int r = (home + tries) % kXcds;
+            const int pn = pencil_of(r, atomicAdd(&pctr[r], 1));
+            if (pn >= 0) return pn;
+            ++tries;
+        }
+        return (int)npen;
+    };
+    // the LDS starts undefined: clear it once; every pencil leaves it clear
+    for (int i = tid; i < lds_words; i += NT) lds[i] = 0;
+    if (tid == 0) {
+        const int j = (int)(blockIdx.x / kXcds);
+        const int64_t p0 = (int64_t)home * run + j;
+        s_pen = (j < run && p0 < npen) ? (int)p0 : claim_next();
+        s_clsbox = -1;
+    }
+    __syncthreads();
+    for (;;) {
+    // uniform: the box constants below stay scalar loads
+    const int pen = __builtin_amdgcn_readfirstlane(s_pen);
+    if (pen >= npen) break;
+    // the next pencil of the home run is claimed now and checked after the
+    // deposition, so the atomic's latency hides behind it
+    int claim = 0;
+    if (tid == 0 && tries < kXcds) claim = atomicAdd(&pctr[(home + tries) % kXcds], 1);
     const int64_t n = *stepp;
     const int bi = box_of_block(Bs, nbox, pen, [](const DevBox &b) { return b.blk_t; });
     const DevBox &B = Bs[bi];
@@ -601,11 +652,9 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
     const int PXa = B.pxa;                 // words per unwrapped row (per component)
     int32_t *acc = lds;                    // [T2][T1][PXa][3]
     int *tab = lds + B.lds_tab;            // record-start table of the window
-    const int tid = threadIdx.x, lane = tid & 63;
     const int mlo0 = B.mlo[0], mhi0 = B.mhi[0];
     const int mlo1 = B.mlo[1], mhi1 = B.mhi[1];
     const int mlo2 = B.mlo[2], mhi2 = B.mhi[2];
-    for (int i = tid; i < 3 * T2 * T1 * PXa; i += NT) acc[i] = 0;
     float scale = 1.0f;
     if (n >= M) {
         const int WY = e1 + mhi1 - mlo1;      // window cell rows in y, z
@@ -621,17 +670,19 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
             tab[k] = start[plane + (int64_t)b1 * B.nxb];
         }
         // row classes that some particle can reach: nearest approach of the row to
-        // a base-cell offset in [0, 1)^2 within the cut-off
+        // a base-cell offset in [0, 1)^2 within the cut-off.  They depend on the box
+        // only: kept from the previous pencil of the same box
         const float cut = B.R2f + B.guard;
         const int ny = mhi1 - mlo1 + 1, nz = mhi2 - mlo2 + 1;
+        const bool fresh = s_clsbox != bi;
         if (tid == 0) {
-            s_ncls = 0;
+            if (fresh) s_ncls = 0;
             s_next = 0;
         }
-        if (tid <= mhi0 - mlo0)
+        if (fresh && tid <= mhi0 - mlo0)
             s_q[tid] = exp2f(-2.0f * B.cexp * B.dxf[0] * B.dxf[0] * (float)(mlo0 + tid));
         __syncthreads();
-        if (tid < nz) {
+        if (fresh && tid < nz) {
             // the rows dy of plane dz that some particle reaches form one interval
             // (the test is convex in |dy|); it is cut into bands of KB rows
             const int dz = mlo2 + tid;
@@ -651,6 +702,7 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
             }
         }
         __syncthreads();
+        if (tid == 0) s_clsbox = bi;      // read again only after the pencil's last barrier
         // records of window plane wz, cell rows j in [ja, ja + len): [g0, g1) and,
         // when the rows wrap past Ny, [h0, h1)
         auto ranges = [&](int wz, int ja, int len, int &g0, int &g1, int &h0, int &h1) {
@@ -836,7 +888,9 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
     // store: node x of a pencil row = index x - mlo plus its periodic images
     // x + Nx - mlo (for x < mhi) and x - Nx - mlo (for x >= Nx + mlo).  Each wave
     // stores whole pencil rows, lanes along x, so the row and its place in the
-    // box are wave-uniform and no lane divides
+    // box are wave-uniform and no lane divides.  When the workgroup may take
+    // another pencil, every word it reads is cleared for it (the deposition
+    // writes no other word)
     float *f = (float *)B.f;
     const float inv = 1.0f / scale;
     const int64_t ng = (int64_t)Nx * Ny * Nz;
@@ -849,17 +903,20 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
         for (int x = lane; x < Nx; x += 64) {
             const int a = base + 3 * x;
             int v0 = acc[a], v1 = acc[a + 1], v2 = acc[a + 2];
+            if (again) acc[a] = acc[a + 1] = acc[a + 2] = 0;
             if (x < mhi0) {
                 const int a2 = a + 3 * Nx;
                 v0 += acc[a2];
                 v1 += acc[a2 + 1];
                 v2 += acc[a2 + 2];
+                if (again) acc[a2] = acc[a2 + 1] = acc[a2 + 2] = 0;
             }
             if (x >= Nx + mlo0) {
                 const int a2 = a - 3 * Nx;
                 v0 += acc[a2];
                 v1 += acc[a2 + 1];
                 v2 += acc[a2 + 2];
+                if (again) acc[a2] = acc[a2 + 1] = acc[a2 + 2] = 0;
             }
             fr[x] = (float)v0 * inv;
             fr[ng + x] = (float)v1 * inv;
@@ -871,6 +928,24 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
             ly -= e1;
             ++lz;
         }
+    }
+    // the record-start table too (another box's pencil may lay accumulators there)
+    if (again && n >= M) {
+        const int tw = (e2 + mhi2 - mlo2) * (e1 + mhi1 - mlo1 + 2);
+        for (int k = tid; k < tw; k += NT) tab[k] = 0;
+    }
+    if (tid == 0) {
+        int nxt = (int)npen;
+        if (tries < kXcds) {
+            nxt = pencil_of((home + tries) % kXcds, claim);
+            if (nxt < 0) {
+                ++tries;
+                nxt = claim_next();
+            }
+        }
+        s_pen = nxt;
+    }
+    __syncthreads();
     }
 }
 
@@ -1187,7 +1262,7 @@ hipError_t fast_prepare_bound_lds(size_t bytes) {
 // The scatter instance of a plan: pencil depth TZ (rounded up to a power of
 // two), workgroup size and rows per work item.
 using ScatterFn = void (*)(const DevBox *, int, const int64_t *, int, const int32_t *,
-                           const float4 *, const float *, int64_t, int64_t);
+                           const float4 *, const float *, int64_t, int64_t, int32_t *, int, int);
 
 template <int NT, int KB>
 ScatterFn scatter_fn_tz(int tz) {
@@ -1247,11 +1322,32 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                 const int64_t pgrid = (P->tblocks + kXcds - 1) / kXcds * kXcds;
                 hipLaunchKernelGGL(k_pencil_scale, dim3((unsigned)pgrid), dim3(kBlock),
                                    P->bound_lds, st, P->dbox, P->nbox, P->s.step + 1, P->M,
-                                   P->s.bsum, P->s.pscale, P->tblocks);
-                hipLaunchKernelGGL(fn, dim3((unsigned)pgrid), dim3(big ? 1024 : 512),
+                                   P->s.bsum, P->s.pscale, P->tblocks, P->s.pctr);
+                // one workgroup per pencil, or, when the pencils outnumber the
+                // workgroups the compute units hold at once more than kPersist
+                // times, that many resident workgroups taking pencils in turn (a
+                // multiple of the XCD count): the per-pencil prologue, clearing and
+                // launch then repeat within a workgroup instead of across launches
+                if (P->sgrid_fn != (const void *)fn || P->sgrid_lds != P->lds_bytes) {
+                    int dev = 0, ncu = 0, per = 0;
+                    hipError_t e = hipGetDevice(&dev);
+                    if (e == hipSuccess)
+                        e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+                    if (e == hipSuccess)
+                        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &per, (const void *)fn, big ? 1024 : 512, P->lds_bytes);
+                    if (e != hipSuccess) return e;
+                    P->sgrid = (int64_t)std::max(ncu, 1) * std::max(per, 1);
+                    P->sgrid_fn = (const void *)fn;
+                    P->sgrid_lds = P->lds_bytes;
+                }
+                const int64_t res = std::max<int64_t>(kXcds, P->sgrid / kXcds * kXcds);
+                const int64_t sgrid = pgrid > kPersist * res ? res : pgrid;
+                hipLaunchKernelGGL(fn, dim3((unsigned)sgrid), dim3(big ? 1024 : 512),
                                    P->lds_bytes, st, P->dbox, P->nbox, P->s.step + 1, P->M,
                                    P->s.start, P->s.rec, P->s.pscale, P->tblocks,
-                                   P->np_total);
+                                   P->np_total, P->s.pctr, (int)(pgrid / kXcds),
+                                   (int)(P->lds_bytes / 4));
             }
             break;
         case 4:

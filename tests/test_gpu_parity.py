@@ -334,6 +334,23 @@ def test_batched_uneven_boxes_and_graph():
     _run_parity(boxes, w.M, w.dt, w.M + 4, erpp.F32_FAST, graph=True, tile=(0, 3, 5))
 
 
+def test_scatter_resident_workgroups_across_boxes():
+    """One-row pencils of three boxes (4912 pencils, far more than four per workgroup
+    the chip holds at once) run on resident workgroups that take pencils in turn,
+    across boxes whose x extents, and so LDS layouts, differ: the accumulator and the
+    record-start table a pencil leaves must be clear for the next."""
+    _cuda()
+    w = workloads.config(5, nbox=3)
+    boxes = []
+    for i, spec in enumerate(w.boxes):
+        npb = [3000, 1800, 600][i]
+        n = [(64, 48, 48), (40, 36, 44), (32, 32, 32)][i]
+        spec = workloads.dataclasses.replace(spec, np_=npb, n=n, kmax=8.0,
+                                             L=tuple(2 * math.pi * a / 32 for a in n))
+        boxes.append(workloads.make_box(spec))
+    _run_parity(boxes, w.M, w.dt, w.M + 3, erpp.F32_FAST, graph=True, tile=(512, 1, 1))
+
+
 def test_graph_replay_equals_eager():
     _cuda()
     w = workloads.config(1, np_=700)
