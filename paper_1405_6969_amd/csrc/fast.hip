@@ -36,9 +36,9 @@ namespace {
 // [x G/kXcds, (x + 1) G/kXcds).  A bijection on [0, grid).
 constexpr int kXcds = 8;
 // the scatter runs resident workgroups when its pencils exceed this many per
-// resident workgroup (the 512^3 box: 46 per CU, 5.21 -> 4.76 ms per step; at two
-// per CU, as on the 256 x 128 x 128 box, one workgroup per pencil is as fast)
-constexpr int64_t kPersist = 4;
+// resident workgroup (the 512^3 box: 46 per CU, 5.21 -> 4.76 ms per step; at 7 per
+// CU, as on the 256^3 box, it measured 1% slower, at 2 the same)
+constexpr int64_t kPersist = 8;
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t grid) {
     return (b % kXcds) * (grid / kXcds) + b / kXcds;
 }
@@ -578,8 +578,9 @@ __device__ __forceinline__ uint32_t fixed32(float v) {
 // adds.
 // TZ: the plan's pencil depth rounded up to a power of two (>= every box's T2);
 // a row class has at most 2 TZ record ranges.  NT: threads per workgroup.  KB:
-// rows per work item.
-template <int TZ, int NT, int KB>
+// rows per work item.  RES: resident workgroups taking pencils in turn (else one
+// workgroup per pencil, the grid padded to a multiple of 8).
+template <int TZ, int NT, int KB, bool RES>
 __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
                                                            int nbox,
                                                            const int64_t *__restrict__ stepp,
@@ -604,10 +605,10 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
     // first: its first pencil by its index (the first gridDim/8 pencils of every
     // run), the rest from the run's counter, then the other runs in turn.  Every
     // workgroup ends once all runs are drained, whatever XCD it landed on.  With
-    // one workgroup per pencil (gridDim/8 = run) no counter is touched.
+    // one workgroup per pencil (RES false, gridDim/8 = run) no counter is touched.
     const int home = (int)(blockIdx.x % kXcds);
     const int first = (int)(gridDim.x / kXcds);
-    const bool again = first < run;       // a workgroup may take more than one pencil
+    constexpr bool again = RES;           // a workgroup may take more than one pencil
     int tries = again ? 0 : kXcds;        // runs found drained (thread 0)
     auto pencil_of = [&](int r, int i) -> int {
         const int64_t pn = (int64_t)r * run + first + i;
@@ -622,18 +623,27 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
         }
         return (int)npen;
     };
-    // the LDS starts undefined: clear it once; every pencil leaves it clear
+    // the LDS starts undefined: clear it once; every pencil leaves it clear (the
+    // barriers before its first use order the clearing)
     for (int i = tid; i < lds_words; i += NT) lds[i] = 0;
-    if (tid == 0) {
-        const int j = (int)(blockIdx.x / kXcds);
-        const int64_t p0 = (int64_t)home * run + j;
-        s_pen = (j < run && p0 < npen) ? (int)p0 : claim_next();
-        s_clsbox = -1;
+    // the first pencil from the workgroup's index: uniform, so the box constants
+    // below are scalar loads issued at once (no LDS round trip); a resident
+    // workgroup past the end of its run claims one instead
+    const int j = (int)(blockIdx.x / kXcds);
+    const int64_t p0 = (int64_t)home * run + j;
+    int pen = (j < run && p0 < npen) ? (int)p0 : -1;
+    if (again) {
+        if (tid == 0) {
+            s_clsbox = -1;
+            if (pen < 0) s_pen = claim_next();
+        }
+        __syncthreads();
+        if (pen < 0) pen = __builtin_amdgcn_readfirstlane(s_pen);
+    } else if (pen < 0) {
+        return;                           // past the last pencil
     }
-    __syncthreads();
+    (void)first;
     for (;;) {
-    // uniform: the box constants below stay scalar loads
-    const int pen = __builtin_amdgcn_readfirstlane(s_pen);
     if (pen >= npen) break;
     // the next pencil of the home run is claimed now and checked after the
     // deposition, so the atomic's latency hides behind it
@@ -674,7 +684,7 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
         // only: kept from the previous pencil of the same box
         const float cut = B.R2f + B.guard;
         const int ny = mhi1 - mlo1 + 1, nz = mhi2 - mlo2 + 1;
-        const bool fresh = s_clsbox != bi;
+        const bool fresh = !again || s_clsbox != bi;
         if (tid == 0) {
             if (fresh) s_ncls = 0;
             s_next = 0;
@@ -702,7 +712,7 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
             }
         }
         __syncthreads();
-        if (tid == 0) s_clsbox = bi;      // read again only after the pencil's last barrier
+        if (again && tid == 0) s_clsbox = bi;  // read again only after the pencil's last barrier
         // records of window plane wz, cell rows j in [ja, ja + len): [g0, g1) and,
         // when the rows wrap past Ny, [h0, h1)
         auto ranges = [&](int wz, int ja, int len, int &g0, int &g1, int &h0, int &h1) {
@@ -929,8 +939,9 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
             ++lz;
         }
     }
+    if (!again) break;
     // the record-start table too (another box's pencil may lay accumulators there)
-    if (again && n >= M) {
+    if (n >= M) {
         const int tw = (e2 + mhi2 - mlo2) * (e1 + mhi1 - mlo1 + 2);
         for (int k = tid; k < tw; k += NT) tab[k] = 0;
     }
@@ -946,6 +957,7 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
         s_pen = nxt;
     }
     __syncthreads();
+    pen = __builtin_amdgcn_readfirstlane(s_pen);
     }
 }
 
@@ -1264,35 +1276,37 @@ hipError_t fast_prepare_bound_lds(size_t bytes) {
 using ScatterFn = void (*)(const DevBox *, int, const int64_t *, int, const int32_t *,
                            const float4 *, const float *, int64_t, int64_t, int32_t *, int, int);
 
-template <int NT, int KB>
+template <int NT, int KB, bool RES>
 ScatterFn scatter_fn_tz(int tz) {
-    return tz <= 1   ? k_scatter<1, NT, KB>
-         : tz <= 2 ? k_scatter<2, NT, KB>
-         : tz <= 4 ? k_scatter<4, NT, KB>
-                   : k_scatter<8, NT, KB>;
+    return tz <= 1   ? k_scatter<1, NT, KB, RES>
+         : tz <= 2 ? k_scatter<2, NT, KB, RES>
+         : tz <= 4 ? k_scatter<4, NT, KB, RES>
+                   : k_scatter<8, NT, KB, RES>;
 }
 
-template <int NT>
+template <int NT, bool RES>
 ScatterFn scatter_fn_nt(int tz, int band) {
     static_assert(kMinBand == 2 && kMaxBand == 4, "instances below cover kMinBand..kMaxBand");
-    return band <= 2 ? scatter_fn_tz<NT, 2>(tz)
-         : band == 3 ? scatter_fn_tz<NT, 3>(tz)
-                     : scatter_fn_tz<NT, 4>(tz);
+    return band <= 2 ? scatter_fn_tz<NT, 2, RES>(tz)
+         : band == 3 ? scatter_fn_tz<NT, 3, RES>(tz)
+                     : scatter_fn_tz<NT, 4, RES>(tz);
 }
 
-ScatterFn scatter_fn(int tz, bool big, int band) {
-    return big ? scatter_fn_nt<1024>(tz, band) : scatter_fn_nt<512>(tz, band);
+ScatterFn scatter_fn(int tz, bool big, int band, bool res) {
+    if (res) return big ? scatter_fn_nt<1024, true>(tz, band) : scatter_fn_nt<512, true>(tz, band);
+    return big ? scatter_fn_nt<1024, false>(tz, band) : scatter_fn_nt<512, false>(tz, band);
 }
 
 hipError_t fast_prepare_lds(size_t bytes) {
-    for (int big = 0; big < 2; ++big)
-        for (int tz = 1; tz <= 8; tz *= 2)
-            for (int band = kMinBand; band <= kMaxBand; ++band) {
-                hipError_t e = hipFuncSetAttribute((const void *)scatter_fn(tz, big != 0, band),
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                   (int)bytes);
-                if (e != hipSuccess) return e;
-            }
+    for (int res = 0; res < 2; ++res)
+        for (int big = 0; big < 2; ++big)
+            for (int tz = 1; tz <= 8; tz *= 2)
+                for (int band = kMinBand; band <= kMaxBand; ++band) {
+                    hipError_t e = hipFuncSetAttribute(
+                        (const void *)scatter_fn(tz, big != 0, band, res != 0),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+                    if (e != hipSuccess) return e;
+                }
     return hipSuccess;
 }
 
@@ -1315,7 +1329,7 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
         case 3:
             {
                 const bool big = P->tile[0] == 1024;
-                const ScatterFn fn = scatter_fn(P->tile[2], big, P->band);
+                const ScatterFn rfn = scatter_fn(P->tile[2], big, P->band, true);
                 hipLaunchKernelGGL(k_block_sums, dim3((unsigned)P->bblocks), dim3(kBlock), 0, st,
                                    P->dbox, P->nbox, P->s.step + 1, P->M, P->s.start, P->s.rec,
                                    P->s.bsum);
@@ -1328,21 +1342,23 @@ hipError_t fast_stage(erpp_plan *P, int k, hipStream_t st) {
                 // times, that many resident workgroups taking pencils in turn (a
                 // multiple of the XCD count): the per-pencil prologue, clearing and
                 // launch then repeat within a workgroup instead of across launches
-                if (P->sgrid_fn != (const void *)fn || P->sgrid_lds != P->lds_bytes) {
+                if (P->sgrid_fn != (const void *)rfn || P->sgrid_lds != P->lds_bytes) {
                     int dev = 0, ncu = 0, per = 0;
                     hipError_t e = hipGetDevice(&dev);
                     if (e == hipSuccess)
                         e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
                     if (e == hipSuccess)
                         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                            &per, (const void *)fn, big ? 1024 : 512, P->lds_bytes);
+                            &per, (const void *)rfn, big ? 1024 : 512, P->lds_bytes);
                     if (e != hipSuccess) return e;
                     P->sgrid = (int64_t)std::max(ncu, 1) * std::max(per, 1);
-                    P->sgrid_fn = (const void *)fn;
+                    P->sgrid_fn = (const void *)rfn;
                     P->sgrid_lds = P->lds_bytes;
                 }
                 const int64_t res = std::max<int64_t>(kXcds, P->sgrid / kXcds * kXcds);
-                const int64_t sgrid = pgrid > kPersist * res ? res : pgrid;
+                const bool resident = pgrid > kPersist * res;
+                const ScatterFn fn = resident ? rfn : scatter_fn(P->tile[2], big, P->band, false);
+                const int64_t sgrid = resident ? res : pgrid;
                 hipLaunchKernelGGL(fn, dim3((unsigned)sgrid), dim3(big ? 1024 : 512),
                                    P->lds_bytes, st, P->dbox, P->nbox, P->s.step + 1, P->M,
                                    P->s.start, P->s.rec, P->s.pscale, P->tblocks,

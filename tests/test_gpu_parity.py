@@ -335,8 +335,8 @@ def test_batched_uneven_boxes_and_graph():
 
 
 def test_scatter_resident_workgroups_across_boxes():
-    """One-row pencils of three boxes (4912 pencils, far more than four per workgroup
-    the chip holds at once) run on resident workgroups that take pencils in turn,
+    """One-row pencils of three boxes (9008 pencils, more than eight per workgroup the
+    chip holds at once) run on resident workgroups that take pencils in turn,
     across boxes whose x extents, and so LDS layouts, differ: the accumulator and the
     record-start table a pencil leaves must be clear for the next."""
     _cuda()
@@ -344,7 +344,7 @@ def test_scatter_resident_workgroups_across_boxes():
     boxes = []
     for i, spec in enumerate(w.boxes):
         npb = [3000, 1800, 600][i]
-        n = [(64, 48, 48), (40, 36, 44), (32, 32, 32)][i]
+        n = [(64, 80, 80), (40, 36, 44), (32, 32, 32)][i]
         spec = workloads.dataclasses.replace(spec, np_=npb, n=n, kmax=8.0,
                                              L=tuple(2 * math.pi * a / 32 for a in n))
         boxes.append(workloads.make_box(spec))
