@@ -107,14 +107,14 @@ def stencil_nodes_of(box):
 
 
 def kernel_source_hash():
-    """Hash of the fast path's kernel sources with // comments and blank lines
-    dropped: a change of code, not of its comments, invalidates the recorded
-    counter summary."""
+    """Hash of the fast path's kernel sources with // comments, indentation and
+    blank lines dropped: a change of code, not of its comments or layout,
+    invalidates the recorded counter summary."""
     h = hashlib.sha256()
     for name in ("fast.hip", "erpp_device.hpp", "erpp_internal.hpp"):
         with open(os.path.join(ROOT, "paper_1405_6969_amd", "csrc", name)) as fh:
             for line in fh:
-                code = line.split("//", 1)[0].rstrip()
+                code = line.split("//", 1)[0].strip()
                 if code:
                     h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]

@@ -642,322 +642,321 @@ __global__ void __launch_bounds__(NT) k_scatter(const DevBox *__restrict__ Bs,
     } else if (pen < 0) {
         return;                           // past the last pencil
     }
-    (void)first;
     for (;;) {
-    if (pen >= npen) break;
-    // the next pencil of the home run is claimed now and checked after the
-    // deposition, so the atomic's latency hides behind it
-    int claim = 0;
-    if (tid == 0 && tries < kXcds) claim = atomicAdd(&pctr[(home + tries) % kXcds], 1);
-    const int64_t n = *stepp;
-    const int bi = box_of_block(Bs, nbox, pen, [](const DevBox &b) { return b.blk_t; });
-    const DevBox &B = Bs[bi];
-    const int t = (int)(pen - B.blk_t);
-    const int T1 = B.T[1], T2 = B.T[2];
-    const int o1 = (t % B.ntile[1]) * T1;
-    const int o2 = (t / B.ntile[1]) * T2;
-    const int Nx = B.n[0], Ny = B.n[1], Nz = B.n[2];
-    const int e1 = min(T1, Ny - o1);
-    const int e2 = min(T2, Nz - o2);
-    const int PXa = B.pxa;                 // words per unwrapped row (per component)
-    int32_t *acc = lds;                    // [T2][T1][PXa][3]
-    int *tab = lds + B.lds_tab;            // record-start table of the window
-    const int mlo0 = B.mlo[0], mhi0 = B.mhi[0];
-    const int mlo1 = B.mlo[1], mhi1 = B.mhi[1];
-    const int mlo2 = B.mlo[2], mhi2 = B.mhi[2];
-    float scale = 1.0f;
-    if (n >= M) {
-        const int WY = e1 + mhi1 - mlo1;      // window cell rows in y, z
-        const int WZ = e2 + mhi2 - mlo2;
-        const int TW = WY + 2;                // table row: WY + 1 row starts, then end of plane
-        // tab[wz][j] = first record of cell row b1 = (o1 - mhi1 + j) mod Ny of window
-        // plane b2 = (o2 - mhi2 + wz) mod Nz, j <= WY; tab[wz][WY + 1] = end of the plane
-        for (int k = tid; k < WZ * TW; k += NT) {
-            const int wz = k / TW, j = k - wz * TW;
-            const int b2 = wrap_index(o2 - mhi2 + wz, Nz);
-            const int64_t plane = B.key_off + (int64_t)b2 * Ny * B.nxb;
-            const int b1 = (j <= WY) ? wrap_index(o1 - mhi1 + j, Ny) : Ny;
-            tab[k] = start[plane + (int64_t)b1 * B.nxb];
-        }
-        // row classes that some particle can reach: nearest approach of the row to
-        // a base-cell offset in [0, 1)^2 within the cut-off.  They depend on the box
-        // only: kept from the previous pencil of the same box
-        const float cut = B.R2f + B.guard;
-        const int ny = mhi1 - mlo1 + 1, nz = mhi2 - mlo2 + 1;
-        const bool fresh = !again || s_clsbox != bi;
-        if (tid == 0) {
-            if (fresh) s_ncls = 0;
-            s_next = 0;
-        }
-        if (fresh && tid <= mhi0 - mlo0)
-            s_q[tid] = exp2f(-2.0f * B.cexp * B.dxf[0] * B.dxf[0] * (float)(mlo0 + tid));
-        __syncthreads();
-        if (fresh && tid < nz) {
-            // the rows dy of plane dz that some particle reaches form one interval
-            // (the test is convex in |dy|); it is cut into bands of KB rows
-            const int dz = mlo2 + tid;
-            const float az = (float)(dz >= 1 ? dz - 1 : -dz) * B.dxf[2];
-            int lo = 1 << 20, hi = -(1 << 20);
-            for (int k = 0; k < ny; ++k) {
-                const int dy = mlo1 + k;
-                const float ay = (float)(dy >= 1 ? dy - 1 : -dy) * B.dxf[1];
-                if (fmaf(ay, ay, az * az) <= cut) {
-                    lo = min(lo, dy);
-                    hi = max(hi, dy);
-                }
+        if (pen >= npen) break;
+        // the next pencil of the home run is claimed now and checked after the
+        // deposition, so the atomic's latency hides behind it
+        int claim = 0;
+        if (tid == 0 && tries < kXcds) claim = atomicAdd(&pctr[(home + tries) % kXcds], 1);
+        const int64_t n = *stepp;
+        const int bi = box_of_block(Bs, nbox, pen, [](const DevBox &b) { return b.blk_t; });
+        const DevBox &B = Bs[bi];
+        const int t = (int)(pen - B.blk_t);
+        const int T1 = B.T[1], T2 = B.T[2];
+        const int o1 = (t % B.ntile[1]) * T1;
+        const int o2 = (t / B.ntile[1]) * T2;
+        const int Nx = B.n[0], Ny = B.n[1], Nz = B.n[2];
+        const int e1 = min(T1, Ny - o1);
+        const int e2 = min(T2, Nz - o2);
+        const int PXa = B.pxa;                 // words per unwrapped row (per component)
+        int32_t *acc = lds;                    // [T2][T1][PXa][3]
+        int *tab = lds + B.lds_tab;            // record-start table of the window
+        const int mlo0 = B.mlo[0], mhi0 = B.mhi[0];
+        const int mlo1 = B.mlo[1], mhi1 = B.mhi[1];
+        const int mlo2 = B.mlo[2], mhi2 = B.mhi[2];
+        float scale = 1.0f;
+        if (n >= M) {
+            const int WY = e1 + mhi1 - mlo1;      // window cell rows in y, z
+            const int WZ = e2 + mhi2 - mlo2;
+            const int TW = WY + 2;                // table row: WY + 1 row starts, then end of plane
+            // tab[wz][j] = first record of cell row b1 = (o1 - mhi1 + j) mod Ny of window
+            // plane b2 = (o2 - mhi2 + wz) mod Nz, j <= WY; tab[wz][WY + 1] = end of the plane
+            for (int k = tid; k < WZ * TW; k += NT) {
+                const int wz = k / TW, j = k - wz * TW;
+                const int b2 = wrap_index(o2 - mhi2 + wz, Nz);
+                const int64_t plane = B.key_off + (int64_t)b2 * Ny * B.nxb;
+                const int b1 = (j <= WY) ? wrap_index(o1 - mhi1 + j, Ny) : Ny;
+                tab[k] = start[plane + (int64_t)b1 * B.nxb];
             }
-            for (int dy0 = lo; dy0 <= hi; dy0 += KB) {
-                const int nb = min(KB, hi - dy0 + 1);
-                s_cls[atomicAdd(&s_ncls, 1)] = (dz + 64) | ((dy0 + 64) << 8) | (nb << 16);
+            // row classes that some particle can reach: nearest approach of the row to
+            // a base-cell offset in [0, 1)^2 within the cut-off.  They depend on the box
+            // only: kept from the previous pencil of the same box
+            const float cut = B.R2f + B.guard;
+            const int ny = mhi1 - mlo1 + 1, nz = mhi2 - mlo2 + 1;
+            const bool fresh = !again || s_clsbox != bi;
+            if (tid == 0) {
+                if (fresh) s_ncls = 0;
+                s_next = 0;
             }
-        }
-        __syncthreads();
-        if (again && tid == 0) s_clsbox = bi;  // read again only after the pencil's last barrier
-        // records of window plane wz, cell rows j in [ja, ja + len): [g0, g1) and,
-        // when the rows wrap past Ny, [h0, h1)
-        auto ranges = [&](int wz, int ja, int len, int &g0, int &g1, int &h0, int &h1) {
-            const int *T = tab + wz * TW;
-            const int b1a = wrap_index(o1 - mhi1 + ja, Ny);
-            g0 = T[ja];
-            if (b1a + len <= Ny) {
-                g1 = (b1a + len == Ny) ? T[WY + 1] : T[ja + len];
-                h0 = h1 = 0;
-            } else {
-                g1 = T[WY + 1];
-                h0 = T[ja + (Ny - b1a)];
-                h1 = T[ja + len];
-            }
-        };
-        // fixed-point scale of the pencil (k_pencil_scale)
-        scale = pscale[pen];
-        // the records through a buffer resource: 32-bit byte offsets
-        const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)rec, (short)0, (int)(32 * npart), kBufferWord3);
-        const int64_t slot = (n - M) % (M + 1);
-        float hx = B.dxf[0], hy = B.dxf[1], hz = B.dxf[2];
-        float c = B.cexp;
-        const float qx = exp2f(-2.0f * c * hx * hx);
-        const float chx2 = c * hx * hx;
-        // box constants of the row loop, pinned in registers: reloading them from
-        // the box descriptor inside the loop would wait on the LDS counter, i.e.
-        // on the previous row's atomics
-        RowK K = row_consts(B);
-        float cutv = cut;
-        asm volatile("" : "+v"(K.R2f), "+v"(K.guard), "+v"(K.idx0), "+v"(K.dx0), "+v"(K.gs));
-        asm volatile("" : "+v"(K.mlo0), "+v"(K.mhi0), "+v"(hx), "+v"(hy), "+v"(hz), "+v"(c),
-                     "+v"(cutv));
-        const int ncls = s_ncls;
-        const int nr = 2 * e2;
-        // classes are handed out to the waves as they finish the previous one (the
-        // classes differ in size, so a fixed round-robin leaves waves idle at the end)
-        for (;;) {
-            int cn = 0;
-            if (lane == 0) cn = atomicAdd(&s_next, 1);
-            const int ci = __builtin_amdgcn_readfirstlane(cn);
-            if (ci >= ncls) break;
-            const int clw = s_cls[ci];
-            const int dz = (clw & 255) - 64, dy0 = ((clw >> 8) & 255) - 64, nb = clw >> 16;
-            // rows dy0 .. dy0 + nb - 1 of plane dz.  The records whose band reaches the
-            // pencil: cell rows b1 in [o1 - dy0 - nb + 1, o1 - dy0 + e1), window rows
-            // ja .. ja + len - 1.  Lane k < 2 e2: part (k & 1) of the records of plane
-            // k >> 1; part 0 holds cell rows b1 in [b1a, ...), part 1 (wrapped past
-            // Ny) b1 in [0, ...).  A record's window row is b1 + jo (jo uniform over
-            // the range); its row dy0 + r lands on pencil row b1 + jo + r - nb + 1
-            // and LDS node index b1 PXa + b0 + m + rowoff + r PXa.
-            const int ja = mhi1 - dy0 - nb + 1, wlen = e1 + nb - 1;
-            const int b1a = wrap_index(o1 - dy0 - nb + 1, Ny);
-            int len = 0, gb = 0, rowoff = 0, jo = 0;
-            if (lane < nr) {
-                int g0, g1, h0, h1;
-                ranges((lane >> 1) + mhi2 - dz, ja, wlen, g0, g1, h0, h1);
-                gb = (lane & 1) ? h0 : g0;
-                len = (lane & 1) ? h1 - h0 : g1 - g0;
-                jo = -b1a + ((lane & 1) ? Ny : 0);
-                rowoff = ((lane >> 1) * T1 + jo - nb + 1) * PXa - mlo0;
-            }
-            const int incl = wave_incl_scan(len);
-            const int total = __shfl(incl, 63, 64);
-            if (total == 0) continue;
-            // item q of range k is record q + off_k (pre_k <= q < pre_k + len_k)
-            const int pre = incl - len;
-            const int off = gb - pre;
-            constexpr int kMaxRanges = 2 * TZ;
-            int pre_k[kMaxRanges], off_k[kMaxRanges], row_k[kMaxRanges], jo_k[kMaxRanges];
-#pragma unroll
-            for (int k = 0; k < kMaxRanges; ++k) {
-                pre_k[k] = __builtin_amdgcn_readlane(pre, k);
-                off_k[k] = __builtin_amdgcn_readlane(off, k);
-                row_k[k] = __builtin_amdgcn_readlane(rowoff, k);
-                jo_k[k] = __builtin_amdgcn_readlane(jo, k);
-            }
-            // byte offset of item q's record, and the LDS row offset and window-row
-            // offset of its range
-            auto record_of = [&](int q, int &ro, int &jr) -> int {
-                int o = off_k[0];
-                ro = row_k[0];
-                jr = jo_k[0];
-#pragma unroll
-                for (int k = 1; k < kMaxRanges; ++k)
-                    if (k < nr && q >= pre_k[k]) {
-                        o = off_k[k];
-                        ro = row_k[k];
-                        jr = jo_k[k];
+            if (fresh && tid <= mhi0 - mlo0)
+                s_q[tid] = exp2f(-2.0f * B.cexp * B.dxf[0] * B.dxf[0] * (float)(mlo0 + tid));
+            __syncthreads();
+            if (fresh && tid < nz) {
+                // the rows dy of plane dz that some particle reaches form one interval
+                // (the test is convex in |dy|); it is cut into bands of KB rows
+                const int dz = mlo2 + tid;
+                const float az = (float)(dz >= 1 ? dz - 1 : -dz) * B.dxf[2];
+                int lo = 1 << 20, hi = -(1 << 20);
+                for (int k = 0; k < ny; ++k) {
+                    const int dy = mlo1 + k;
+                    const float ay = (float)(dy >= 1 ? dy - 1 : -dy) * B.dxf[1];
+                    if (fmaf(ay, ay, az * az) <= cut) {
+                        lo = min(lo, dy);
+                        hi = max(hi, dy);
                     }
-                return (q + o) << 5;
-            };
-            // lane l takes the items [l P, l P + P): the lanes of one pass are spread
-            // over the whole range, so fewer of them add into the same node or bank
-            const int P = (total + 63) >> 6;
-            int q = lane * P;
-            const int qend = min(q + P, total);
-            // one band of an item: per row the pencil test, the sphere test, the
-            // range, the first weight, then the node walk
-            const float tzc = (float)dz;
-            auto band = [&](const float4 qa, const float4 qb, const int ro, const int jr) {
-                const uint32_t ijk = __float_as_uint(qa.w);
-                const int b0 = (int)(ijk & 2047u);
-                const int b1 = (int)((ijk >> 11) & 2047u);
-                const int rowx = (int)__umul24((unsigned)b1, (unsigned)PXa) + b0 + ro;
-                const int y0 = b1 + jr - nb + 1;          // pencil row of the band's first row
-                const float tzv = (tzc - qa.z) * hz;
-                const float tz2 = tzv * tzv;
-                // ratio w(m + 1) / w(m) along a row is exp2(c hx^2 (2 phi_x - 1)) times
-                // s_q[m - mlo] = exp2(-2 c hx^2 m); the amplitudes carry the scale
-                const float ra = __builtin_amdgcn_exp2f(chx2 * fmaf(2.0f, qa.x, -1.0f));
-                const float sax = qb.x * scale, say = qb.y * scale, saz = qb.z * scale;
-#pragma unroll
-                for (int r = 0; r < KB; ++r) {
-                    if (r >= nb) break;
-                    const int y = y0 + r;
-                    if (y < 0 || y >= e1) continue;
-                    const int dy = dy0 + r;
-                    const float tyv = d1(dy, qa.y, hy);
-                    const float ryz = fmaf(tyv, tyv, tz2);
-                    if (ryz > cutv) continue;
-                    int rlo, rhi;
-                    row_range(qa.x, ryz, K, &B, slot, __float_as_int(qb.w), dy, dz, rlo, rhi);
-                    if (rlo > rhi) continue;
-                    // raw v_exp_f32: the argument lies in [-2 R^2 c, 0], far from underflow
-                    const float t0 = ((float)rlo - qa.x) * hx;
-                    const float w = __builtin_amdgcn_exp2f(-fmaf(t0, t0, ryz) * c);
-                    // weight ratio of the first step along the row: the item's factor
-                    // times the tabulated power of the first node
-                    float rr = ra * s_q[rlo - K.mlo0];
-                    // contributions a_c w of the row's first node, advanced along the row
-                    // by the weight ratio rr (itself advanced by qx)
-                    float cx = sax * w, cy = say * w, cz = saz * w;
-                    int a = 3 * (rowx + rlo + r * PXa);
-                    int cntn = rhi - rlo + 1;
-                    do {
-                        atomicAdd((uint32_t *)&lds[a], fixed32(cx));
-                        atomicAdd((uint32_t *)&lds[a + 1], fixed32(cy));
-                        atomicAdd((uint32_t *)&lds[a + 2], fixed32(cz));
-                        cx *= rr;
-                        cy *= rr;
-                        cz *= rr;
-                        rr *= qx;
-                        a += 3;
-                    } while (--cntn != 0);
                 }
-            };
-            // records are fetched one item ahead into two register sets used in
-            // turn (no copies between them).  The fetch is unconditional (the last
-            // item re-reads its own record) and each set is pinned before the next
-            // fetch is issued, so the wait for a set never waits for the younger
-            // fetch behind it.
-            float4 ra0, rb0, ra1, rb1;
-            int ro0 = 0, ro1 = 0, jr0 = 0, jr1 = 0;
-            if (q < qend) {
-                const int g = record_of(q, ro0, jr0);
-                ra0 = rec_load(rsrc, g);
-                rb0 = rec_load(rsrc, g + 16);
+                for (int dy0 = lo; dy0 <= hi; dy0 += KB) {
+                    const int nb = min(KB, hi - dy0 + 1);
+                    s_cls[atomicAdd(&s_ncls, 1)] = (dz + 64) | ((dy0 + 64) << 8) | (nb << 16);
+                }
             }
-            while (q < qend) {
-                pin4(ra0);
-                pin4(rb0);
-                {
-                    const int g = record_of(min(q + 1, qend - 1), ro1, jr1);
-                    ra1 = rec_load(rsrc, g);
-                    rb1 = rec_load(rsrc, g + 16);
+            __syncthreads();
+            if (again && tid == 0) s_clsbox = bi;  // read again only after the pencil's last barrier
+            // records of window plane wz, cell rows j in [ja, ja + len): [g0, g1) and,
+            // when the rows wrap past Ny, [h0, h1)
+            auto ranges = [&](int wz, int ja, int len, int &g0, int &g1, int &h0, int &h1) {
+                const int *T = tab + wz * TW;
+                const int b1a = wrap_index(o1 - mhi1 + ja, Ny);
+                g0 = T[ja];
+                if (b1a + len <= Ny) {
+                    g1 = (b1a + len == Ny) ? T[WY + 1] : T[ja + len];
+                    h0 = h1 = 0;
+                } else {
+                    g1 = T[WY + 1];
+                    h0 = T[ja + (Ny - b1a)];
+                    h1 = T[ja + len];
                 }
-                band(ra0, rb0, ro0, jr0);
-                if (++q >= qend) break;
-                pin4(ra1);
-                pin4(rb1);
-                {
-                    const int g = record_of(min(q + 1, qend - 1), ro0, jr0);
+            };
+            // fixed-point scale of the pencil (k_pencil_scale)
+            scale = pscale[pen];
+            // the records through a buffer resource: 32-bit byte offsets
+            const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)rec, (short)0, (int)(32 * npart), kBufferWord3);
+            const int64_t slot = (n - M) % (M + 1);
+            float hx = B.dxf[0], hy = B.dxf[1], hz = B.dxf[2];
+            float c = B.cexp;
+            const float qx = exp2f(-2.0f * c * hx * hx);
+            const float chx2 = c * hx * hx;
+            // box constants of the row loop, pinned in registers: reloading them from
+            // the box descriptor inside the loop would wait on the LDS counter, i.e.
+            // on the previous row's atomics
+            RowK K = row_consts(B);
+            float cutv = cut;
+            asm volatile("" : "+v"(K.R2f), "+v"(K.guard), "+v"(K.idx0), "+v"(K.dx0), "+v"(K.gs));
+            asm volatile("" : "+v"(K.mlo0), "+v"(K.mhi0), "+v"(hx), "+v"(hy), "+v"(hz), "+v"(c),
+                         "+v"(cutv));
+            const int ncls = s_ncls;
+            const int nr = 2 * e2;
+            // classes are handed out to the waves as they finish the previous one (the
+            // classes differ in size, so a fixed round-robin leaves waves idle at the end)
+            for (;;) {
+                int cn = 0;
+                if (lane == 0) cn = atomicAdd(&s_next, 1);
+                const int ci = __builtin_amdgcn_readfirstlane(cn);
+                if (ci >= ncls) break;
+                const int clw = s_cls[ci];
+                const int dz = (clw & 255) - 64, dy0 = ((clw >> 8) & 255) - 64, nb = clw >> 16;
+                // rows dy0 .. dy0 + nb - 1 of plane dz.  The records whose band reaches the
+                // pencil: cell rows b1 in [o1 - dy0 - nb + 1, o1 - dy0 + e1), window rows
+                // ja .. ja + len - 1.  Lane k < 2 e2: part (k & 1) of the records of plane
+                // k >> 1; part 0 holds cell rows b1 in [b1a, ...), part 1 (wrapped past
+                // Ny) b1 in [0, ...).  A record's window row is b1 + jo (jo uniform over
+                // the range); its row dy0 + r lands on pencil row b1 + jo + r - nb + 1
+                // and LDS node index b1 PXa + b0 + m + rowoff + r PXa.
+                const int ja = mhi1 - dy0 - nb + 1, wlen = e1 + nb - 1;
+                const int b1a = wrap_index(o1 - dy0 - nb + 1, Ny);
+                int len = 0, gb = 0, rowoff = 0, jo = 0;
+                if (lane < nr) {
+                    int g0, g1, h0, h1;
+                    ranges((lane >> 1) + mhi2 - dz, ja, wlen, g0, g1, h0, h1);
+                    gb = (lane & 1) ? h0 : g0;
+                    len = (lane & 1) ? h1 - h0 : g1 - g0;
+                    jo = -b1a + ((lane & 1) ? Ny : 0);
+                    rowoff = ((lane >> 1) * T1 + jo - nb + 1) * PXa - mlo0;
+                }
+                const int incl = wave_incl_scan(len);
+                const int total = __shfl(incl, 63, 64);
+                if (total == 0) continue;
+                // item q of range k is record q + off_k (pre_k <= q < pre_k + len_k)
+                const int pre = incl - len;
+                const int off = gb - pre;
+                constexpr int kMaxRanges = 2 * TZ;
+                int pre_k[kMaxRanges], off_k[kMaxRanges], row_k[kMaxRanges], jo_k[kMaxRanges];
+    #pragma unroll
+                for (int k = 0; k < kMaxRanges; ++k) {
+                    pre_k[k] = __builtin_amdgcn_readlane(pre, k);
+                    off_k[k] = __builtin_amdgcn_readlane(off, k);
+                    row_k[k] = __builtin_amdgcn_readlane(rowoff, k);
+                    jo_k[k] = __builtin_amdgcn_readlane(jo, k);
+                }
+                // byte offset of item q's record, and the LDS row offset and window-row
+                // offset of its range
+                auto record_of = [&](int q, int &ro, int &jr) -> int {
+                    int o = off_k[0];
+                    ro = row_k[0];
+                    jr = jo_k[0];
+    #pragma unroll
+                    for (int k = 1; k < kMaxRanges; ++k)
+                        if (k < nr && q >= pre_k[k]) {
+                            o = off_k[k];
+                            ro = row_k[k];
+                            jr = jo_k[k];
+                        }
+                    return (q + o) << 5;
+                };
+                // lane l takes the items [l P, l P + P): the lanes of one pass are spread
+                // over the whole range, so fewer of them add into the same node or bank
+                const int P = (total + 63) >> 6;
+                int q = lane * P;
+                const int qend = min(q + P, total);
+                // one band of an item: per row the pencil test, the sphere test, the
+                // range, the first weight, then the node walk
+                const float tzc = (float)dz;
+                auto band = [&](const float4 qa, const float4 qb, const int ro, const int jr) {
+                    const uint32_t ijk = __float_as_uint(qa.w);
+                    const int b0 = (int)(ijk & 2047u);
+                    const int b1 = (int)((ijk >> 11) & 2047u);
+                    const int rowx = (int)__umul24((unsigned)b1, (unsigned)PXa) + b0 + ro;
+                    const int y0 = b1 + jr - nb + 1;          // pencil row of the band's first row
+                    const float tzv = (tzc - qa.z) * hz;
+                    const float tz2 = tzv * tzv;
+                    // ratio w(m + 1) / w(m) along a row is exp2(c hx^2 (2 phi_x - 1)) times
+                    // s_q[m - mlo] = exp2(-2 c hx^2 m); the amplitudes carry the scale
+                    const float ra = __builtin_amdgcn_exp2f(chx2 * fmaf(2.0f, qa.x, -1.0f));
+                    const float sax = qb.x * scale, say = qb.y * scale, saz = qb.z * scale;
+    #pragma unroll
+                    for (int r = 0; r < KB; ++r) {
+                        if (r >= nb) break;
+                        const int y = y0 + r;
+                        if (y < 0 || y >= e1) continue;
+                        const int dy = dy0 + r;
+                        const float tyv = d1(dy, qa.y, hy);
+                        const float ryz = fmaf(tyv, tyv, tz2);
+                        if (ryz > cutv) continue;
+                        int rlo, rhi;
+                        row_range(qa.x, ryz, K, &B, slot, __float_as_int(qb.w), dy, dz, rlo, rhi);
+                        if (rlo > rhi) continue;
+                        // raw v_exp_f32: the argument lies in [-2 R^2 c, 0], far from underflow
+                        const float t0 = ((float)rlo - qa.x) * hx;
+                        const float w = __builtin_amdgcn_exp2f(-fmaf(t0, t0, ryz) * c);
+                        // weight ratio of the first step along the row: the item's factor
+                        // times the tabulated power of the first node
+                        float rr = ra * s_q[rlo - K.mlo0];
+                        // contributions a_c w of the row's first node, advanced along the row
+                        // by the weight ratio rr (itself advanced by qx)
+                        float cx = sax * w, cy = say * w, cz = saz * w;
+                        int a = 3 * (rowx + rlo + r * PXa);
+                        int cntn = rhi - rlo + 1;
+                        do {
+                            atomicAdd((uint32_t *)&lds[a], fixed32(cx));
+                            atomicAdd((uint32_t *)&lds[a + 1], fixed32(cy));
+                            atomicAdd((uint32_t *)&lds[a + 2], fixed32(cz));
+                            cx *= rr;
+                            cy *= rr;
+                            cz *= rr;
+                            rr *= qx;
+                            a += 3;
+                        } while (--cntn != 0);
+                    }
+                };
+                // records are fetched one item ahead into two register sets used in
+                // turn (no copies between them).  The fetch is unconditional (the last
+                // item re-reads its own record) and each set is pinned before the next
+                // fetch is issued, so the wait for a set never waits for the younger
+                // fetch behind it.
+                float4 ra0, rb0, ra1, rb1;
+                int ro0 = 0, ro1 = 0, jr0 = 0, jr1 = 0;
+                if (q < qend) {
+                    const int g = record_of(q, ro0, jr0);
                     ra0 = rec_load(rsrc, g);
                     rb0 = rec_load(rsrc, g + 16);
                 }
-                band(ra1, rb1, ro1, jr1);
-                ++q;
+                while (q < qend) {
+                    pin4(ra0);
+                    pin4(rb0);
+                    {
+                        const int g = record_of(min(q + 1, qend - 1), ro1, jr1);
+                        ra1 = rec_load(rsrc, g);
+                        rb1 = rec_load(rsrc, g + 16);
+                    }
+                    band(ra0, rb0, ro0, jr0);
+                    if (++q >= qend) break;
+                    pin4(ra1);
+                    pin4(rb1);
+                    {
+                        const int g = record_of(min(q + 1, qend - 1), ro0, jr0);
+                        ra0 = rec_load(rsrc, g);
+                        rb0 = rec_load(rsrc, g + 16);
+                    }
+                    band(ra1, rb1, ro1, jr1);
+                    ++q;
+                }
             }
         }
-    }
-    __syncthreads();
-    // store: node x of a pencil row = index x - mlo plus its periodic images
-    // x + Nx - mlo (for x < mhi) and x - Nx - mlo (for x >= Nx + mlo).  Each wave
-    // stores whole pencil rows, lanes along x, so the row and its place in the
-    // box are wave-uniform and no lane divides.  When the workgroup may take
-    // another pencil, every word it reads is cleared for it (the deposition
-    // writes no other word)
-    float *f = (float *)B.f;
-    const float inv = 1.0f / scale;
-    const int64_t ng = (int64_t)Nx * Ny * Nz;
-    const int nw = NT >> 6;
-    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    int ly = wv % e1, lz = wv / e1;
-    for (int r = wv; r < e1 * e2; r += nw) {
-        float *fr = f + ((int64_t)(o2 + lz) * Ny + (o1 + ly)) * Nx;
-        const int base = 3 * ((lz * T1 + ly) * PXa - mlo0);
-        for (int x = lane; x < Nx; x += 64) {
-            const int a = base + 3 * x;
-            int v0 = acc[a], v1 = acc[a + 1], v2 = acc[a + 2];
-            if (again) acc[a] = acc[a + 1] = acc[a + 2] = 0;
-            if (x < mhi0) {
-                const int a2 = a + 3 * Nx;
-                v0 += acc[a2];
-                v1 += acc[a2 + 1];
-                v2 += acc[a2 + 2];
-                if (again) acc[a2] = acc[a2 + 1] = acc[a2 + 2] = 0;
+        __syncthreads();
+        // store: node x of a pencil row = index x - mlo plus its periodic images
+        // x + Nx - mlo (for x < mhi) and x - Nx - mlo (for x >= Nx + mlo).  Each wave
+        // stores whole pencil rows, lanes along x, so the row and its place in the
+        // box are wave-uniform and no lane divides.  When the workgroup may take
+        // another pencil, every word it reads is cleared for it (the deposition
+        // writes no other word)
+        float *f = (float *)B.f;
+        const float inv = 1.0f / scale;
+        const int64_t ng = (int64_t)Nx * Ny * Nz;
+        const int nw = NT >> 6;
+        const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+        int ly = wv % e1, lz = wv / e1;
+        for (int r = wv; r < e1 * e2; r += nw) {
+            float *fr = f + ((int64_t)(o2 + lz) * Ny + (o1 + ly)) * Nx;
+            const int base = 3 * ((lz * T1 + ly) * PXa - mlo0);
+            for (int x = lane; x < Nx; x += 64) {
+                const int a = base + 3 * x;
+                int v0 = acc[a], v1 = acc[a + 1], v2 = acc[a + 2];
+                if (again) acc[a] = acc[a + 1] = acc[a + 2] = 0;
+                if (x < mhi0) {
+                    const int a2 = a + 3 * Nx;
+                    v0 += acc[a2];
+                    v1 += acc[a2 + 1];
+                    v2 += acc[a2 + 2];
+                    if (again) acc[a2] = acc[a2 + 1] = acc[a2 + 2] = 0;
+                }
+                if (x >= Nx + mlo0) {
+                    const int a2 = a - 3 * Nx;
+                    v0 += acc[a2];
+                    v1 += acc[a2 + 1];
+                    v2 += acc[a2 + 2];
+                    if (again) acc[a2] = acc[a2 + 1] = acc[a2 + 2] = 0;
+                }
+                fr[x] = (float)v0 * inv;
+                fr[ng + x] = (float)v1 * inv;
+                fr[2 * ng + x] = (float)v2 * inv;
             }
-            if (x >= Nx + mlo0) {
-                const int a2 = a - 3 * Nx;
-                v0 += acc[a2];
-                v1 += acc[a2 + 1];
-                v2 += acc[a2 + 2];
-                if (again) acc[a2] = acc[a2 + 1] = acc[a2 + 2] = 0;
-            }
-            fr[x] = (float)v0 * inv;
-            fr[ng + x] = (float)v1 * inv;
-            fr[2 * ng + x] = (float)v2 * inv;
-        }
-        // next row of this wave: r + nw = (lz, ly) advanced by nw rows of e1
-        ly += nw;
-        while (ly >= e1) {
-            ly -= e1;
-            ++lz;
-        }
-    }
-    if (!again) break;
-    // the record-start table too (another box's pencil may lay accumulators there)
-    if (n >= M) {
-        const int tw = (e2 + mhi2 - mlo2) * (e1 + mhi1 - mlo1 + 2);
-        for (int k = tid; k < tw; k += NT) tab[k] = 0;
-    }
-    if (tid == 0) {
-        int nxt = (int)npen;
-        if (tries < kXcds) {
-            nxt = pencil_of((home + tries) % kXcds, claim);
-            if (nxt < 0) {
-                ++tries;
-                nxt = claim_next();
+            // next row of this wave: r + nw = (lz, ly) advanced by nw rows of e1
+            ly += nw;
+            while (ly >= e1) {
+                ly -= e1;
+                ++lz;
             }
         }
-        s_pen = nxt;
-    }
-    __syncthreads();
-    pen = __builtin_amdgcn_readfirstlane(s_pen);
+        if (!again) break;
+        // the record-start table too (another box's pencil may lay accumulators there)
+        if (n >= M) {
+            const int tw = (e2 + mhi2 - mlo2) * (e1 + mhi1 - mlo1 + 2);
+            for (int k = tid; k < tw; k += NT) tab[k] = 0;
+        }
+        if (tid == 0) {
+            int nxt = (int)npen;
+            if (tries < kXcds) {
+                nxt = pencil_of((home + tries) % kXcds, claim);
+                if (nxt < 0) {
+                    ++tries;
+                    nxt = claim_next();
+                }
+            }
+            s_pen = nxt;
+        }
+        __syncthreads();
+        pen = __builtin_amdgcn_readfirstlane(s_pen);
     }
 }
 
