@@ -335,16 +335,17 @@ def test_batched_uneven_boxes_and_graph():
 
 
 def test_scatter_resident_workgroups_across_boxes():
-    """One-row pencils of three boxes (9008 pencils, more than eight per workgroup the
+    """One-row pencils of four boxes (10160 pencils, more than eight per workgroup the
     chip holds at once) run on resident workgroups that take pencils in turn,
-    across boxes whose x extents, and so LDS layouts, differ: the accumulator and the
-    record-start table a pencil leaves must be clear for the next."""
+    across boxes whose x extents, and so LDS layouts, differ, one of them without
+    particles: the accumulator and the record-start table a pencil leaves must be
+    clear for the next."""
     _cuda()
-    w = workloads.config(5, nbox=3)
+    w = workloads.config(5, nbox=4)
     boxes = []
     for i, spec in enumerate(w.boxes):
-        npb = [3000, 1800, 600][i]
-        n = [(64, 80, 80), (40, 36, 44), (32, 32, 32)][i]
+        npb = [3000, 1800, 0, 600][i]
+        n = [(64, 80, 80), (40, 36, 44), (48, 36, 32), (32, 32, 32)][i]
         spec = workloads.dataclasses.replace(spec, np_=npb, n=n, kmax=8.0,
                                              L=tuple(2 * math.pi * a / 32 for a in n))
         boxes.append(workloads.make_box(spec))
